@@ -1,0 +1,524 @@
+// abi.hip -- the extern "C" boundary of libsfcngb: argument checks,
+// workspace layout, and the order of launches of each call.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+hipError_t launch_gather(hipStream_t s, const sfc_particles *in, sfc_particles *out,
+                         const uint32_t *perm, uint32_t *perm_out);
+hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                          SearchBufs &sb, const DensityArgs &a, DevStatus *st, int gm);
+hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                        SearchBufs &sb, const HydroArgs &a, DevStatus *st, int gm);
+hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st, int gm);
+
+struct sfc_ctx {
+    hipStream_t stream;
+    int device;
+    int cu;
+    char err[512];
+    bool bound;
+    sfc_dims dims;
+    char *ws;
+    size_t ws_bytes;
+    DevStatus *st;
+    SortBufs sb;
+    TreeBufs tb;
+    TreeDev td;
+    GroupBufs gb;
+    SearchBufs xb;
+    uint32_t *scan_tmp;
+    int tree_leaf; // n_leaf of the last tree, 0 = none
+    int have_groups;
+    int gm;        // max members of the current groups
+    bool capturing;
+};
+
+struct sfc_graph {
+    hipGraph_t g;
+    hipGraphExec_t e;
+};
+
+namespace {
+
+int fail(sfc_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+int hip_fail(sfc_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, SFC_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+// bump allocator over the workspace (or a size count when base is null)
+struct Bump {
+    char *base;
+    size_t off;
+    template <class T> T *take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int64_t node_capacity(const sfc_dims &d)
+{
+    return d.n + 22 * d.n / ((int64_t)d.n_leaf_min + 1) + d.n_boxes + 64;
+}
+
+int64_t max_chunks(const sfc_dims &d) { return d.n / 64 + d.n_boxes + 1; }
+
+int64_t sort_tiles(const sfc_dims &d) { return (d.n + 4095) / 4096; }
+
+bool dims_ok(const sfc_dims *d)
+{
+    return d && d->n >= 1 && d->n < ((int64_t)1 << 30) && d->n_boxes >= 1 &&
+           d->n_boxes <= 65536 && d->n_boxes <= d->n && d->n_leaf_min >= 1 &&
+           d->t_cand_max >= 64 && d->t_cand_max <= 8192 && d->t_cand_max % 64 == 0 &&
+           node_capacity(*d) < ((int64_t)1 << 31) - 1;
+}
+
+size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
+{
+    Bump b{base, 0};
+    int64_t n = d.n, nb = d.n_boxes, cap = node_capacity(d), mc = max_chunks(d);
+    int64_t nt = sort_tiles(d);
+    DevStatus *st = b.take<DevStatus>(1);
+    SortBufs sb;
+    sb.key_a = b.take<uint64_t>(n);
+    sb.key_b = b.take<uint64_t>(n);
+    sb.val_a = b.take<uint32_t>(n);
+    sb.val_b = b.take<uint32_t>(n);
+    sb.box_a = b.take<uint32_t>(nb > 1 ? n : 1);
+    sb.box_b = b.take<uint32_t>(nb > 1 ? n : 1);
+    sb.hist = b.take<uint32_t>(2 * 256 * nt);
+    int64_t scan_n = n + 1;
+    if (256 * nt > scan_n) scan_n = 256 * nt;
+    if (mc + 1 > scan_n) scan_n = mc + 1;
+    uint32_t *scan_tmp = b.take<uint32_t>(scan_tmp_elems(scan_n));
+    sb.scan_tmp = scan_tmp;
+    TreeBufs tb;
+    tb.lcp = b.take<int8_t>(n);
+    tb.dlev = b.take<int8_t>(n);
+    tb.cnt = b.take<uint32_t>(n + 1);
+    tb.start = b.take<uint32_t>(n + 1);
+    TreeDev td;
+    td.info = b.take<int4>(cap);
+    td.lo = b.take<double4>(cap);
+    td.hi = b.take<double4>(cap);
+    td.parent = b.take<int32_t>(cap);
+    td.nchild = b.take<int32_t>(cap);
+    td.counter = b.take<int32_t>(cap);
+    td.box_root = b.take<int32_t>(nb + 1);
+    td.capacity = (int32_t)cap;
+    GroupBufs gb;
+    gb.flag_scan = b.take<uint32_t>(n + 1);
+    gb.act = b.take<int32_t>(n);
+    gb.chunk_base = b.take<int32_t>(nb + 1);
+    gb.gs_local = b.take<int32_t>(n);
+    gb.gcount = b.take<uint32_t>(mc + 1);
+    gb.gscan = b.take<uint32_t>(mc + 1);
+    gb.goff = b.take<int32_t>(n + 1);
+    gb.n_act = b.take<int32_t>(1);
+    gb.n_groups = b.take<int32_t>(1);
+    gb.max_chunks = mc;
+    SearchBufs xb;
+    xb.it_lo = b.take<double>(n);
+    xb.it_hi = b.take<double>(n);
+    xb.it_n = b.take<int32_t>(n);
+    xb.defer = b.take<int32_t>(n);
+    xb.pf = b.take<float>(n);
+    xb.cs = b.take<float>(n);
+    xb.cu_count = c ? c->cu : 0;
+    if (c && base) {
+        c->st = st;
+        c->sb = sb;
+        c->tb = tb;
+        c->td = td;
+        c->gb = gb;
+        c->xb = xb;
+        c->scan_tmp = scan_tmp;
+    }
+    return (b.off + 255) & ~(size_t)255;
+}
+
+int check_ctx(sfc_ctx *c)
+{
+    if (!c) return SFC_EINVAL;
+    if (!c->bound) return fail(c, SFC_EWORKSPACE, "no workspace bound");
+    return SFC_OK;
+}
+
+int check_particles(sfc_ctx *c, const sfc_particles *p, bool need_state)
+{
+    if (!p) return fail(c, SFC_EINVAL, "particles: NULL");
+    if (p->n != c->dims.n || p->n_boxes != c->dims.n_boxes)
+        return fail(c, SFC_EINVAL, "particles: n=%lld boxes=%d differ from the bound dims (%lld, %d)",
+                    (long long)p->n, p->n_boxes, (long long)c->dims.n, c->dims.n_boxes);
+    if (!p->box_off_host || !p->box_off || !p->box_L)
+        return fail(c, SFC_EINVAL, "particles: box arrays missing");
+    if (p->box_off_host[0] != 0 || p->box_off_host[p->n_boxes] != p->n)
+        return fail(c, SFC_EINVAL, "particles: box_off must start at 0 and end at n");
+    for (int b = 0; b < p->n_boxes; b++)
+        if (p->box_off_host[b + 1] < p->box_off_host[b])
+            return fail(c, SFC_EINVAL, "particles: box_off not monotone at %d", b);
+    if (!p->x || !p->y || !p->z || !p->h || !p->m || !p->active)
+        return fail(c, SFC_EINVAL, "particles: x, y, z, h, m and active are required");
+    if (need_state && (!p->rho || !p->fgrad))
+        return fail(c, SFC_EINVAL, "particles: rho and fgrad are required");
+    return SFC_OK;
+}
+
+PartDev part_dev(const sfc_particles *p)
+{
+    PartDev d;
+    d.n = p->n;
+    d.nb = p->n_boxes;
+    d.box_off = p->box_off;
+    d.box_L = p->box_L;
+    d.x = p->x;
+    d.y = p->y;
+    d.z = p->z;
+    d.h = p->h;
+    d.m = p->m;
+    d.vx = p->vx;
+    d.vy = p->vy;
+    d.vz = p->vz;
+    d.u = p->u;
+    d.rho = p->rho;
+    d.fgrad = p->fgrad;
+    d.active = p->active;
+    d.orig = p->orig;
+    return d;
+}
+
+} // namespace
+
+extern "C" {
+
+int sfc_ctx_create(sfc_ctx **out, void *hip_stream)
+{
+    if (!out) return SFC_EINVAL;
+    *out = nullptr;
+    sfc_ctx *c = new (std::nothrow) sfc_ctx();
+    if (!c) return SFC_EINVAL;
+    memset(c, 0, sizeof(*c));
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return SFC_EHIP;
+    }
+    *out = c;
+    return SFC_OK;
+}
+
+void sfc_ctx_destroy(sfc_ctx *ctx) { delete ctx; }
+
+int sfc_ctx_set_stream(sfc_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return SFC_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return SFC_OK;
+}
+
+const char *sfc_ctx_last_error(const sfc_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+int32_t sfc_ctx_cu_count(const sfc_ctx *ctx) { return ctx ? ctx->cu : 0; }
+
+size_t sfc_workspace_bytes(const sfc_dims *dims)
+{
+    if (!dims_ok(dims)) return 0;
+    return layout(nullptr, *dims, nullptr);
+}
+
+int sfc_workspace_bind(sfc_ctx *ctx, const sfc_dims *dims, void *ws, size_t ws_bytes)
+{
+    if (!ctx) return SFC_EINVAL;
+    if (!dims_ok(dims)) return fail(ctx, SFC_EINVAL, "workspace: invalid dims");
+    if (!ws) return fail(ctx, SFC_EINVAL, "workspace: NULL");
+    if ((uintptr_t)ws % 256 != 0) return fail(ctx, SFC_EINVAL, "workspace: must be 256-byte aligned");
+    size_t need = layout(nullptr, *dims, nullptr);
+    if (ws_bytes < need)
+        return fail(ctx, SFC_EWORKSPACE, "workspace: %zu bytes given, %zu needed", ws_bytes, need);
+    ctx->dims = *dims;
+    ctx->ws = (char *)ws;
+    ctx->ws_bytes = ws_bytes;
+    layout(ctx, *dims, (char *)ws);
+    ctx->bound = true;
+    ctx->tree_leaf = 0;
+    ctx->have_groups = 0;
+    return sfc_status_clear(ctx);
+}
+
+int sfc_status_clear(sfc_ctx *ctx)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    hipError_t e = launch_fill_i32(ctx->stream, (int32_t *)ctx->st, 0,
+                                   (int64_t)(sizeof(DevStatus) / sizeof(int32_t)));
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "status clear");
+}
+
+int sfc_sort(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out, uint64_t *keys_out,
+             uint32_t *perm_out)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if ((r = check_particles(ctx, in, false))) return r;
+    if (!out || !keys_out) return fail(ctx, SFC_EINVAL, "sort: out and keys_out are required");
+    if (out->n != in->n || !out->x || !out->y || !out->z || !out->h || !out->m || !out->active)
+        return fail(ctx, SFC_EINVAL, "sort: out must have n and x, y, z, h, m, active");
+    if (out->x == in->x || out->h == in->h) return fail(ctx, SFC_EINVAL, "sort: in and out alias");
+    if (in->orig && !out->orig) return fail(ctx, SFC_EINVAL, "sort: out->orig missing");
+    hipError_t e = launch_keys(ctx->stream, in, ctx->sb);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sort keys");
+    uint32_t *perm = nullptr;
+    e = launch_radix_sort(ctx->stream, in->n, in->n_boxes, ctx->sb, keys_out, &perm);
+    if (e != hipSuccess) return hip_fail(ctx, e, "radix sort");
+    e = launch_gather(ctx->stream, in, out, perm, perm_out);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gather");
+    ctx->tree_leaf = 0;
+    ctx->have_groups = 0;
+    return SFC_OK;
+}
+
+int tree_build(sfc_ctx *ctx, const sfc_particles *p, const uint64_t *keys, int32_t n_leaf)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if ((r = check_particles(ctx, p, false))) return r;
+    if (!keys) return fail(ctx, SFC_EINVAL, "tree_build: keys NULL");
+    if (n_leaf < ctx->dims.n_leaf_min || n_leaf > 4096)
+        return fail(ctx, SFC_EINVAL, "tree_build: n_leaf %d outside [%d, 4096]", n_leaf,
+                    ctx->dims.n_leaf_min);
+    PartDev pd = part_dev(p);
+    hipError_t e = launch_tree_build(ctx->stream, pd, keys, n_leaf, ctx->tb, ctx->td,
+                                     ctx->scan_tmp, ctx->st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tree_build");
+    ctx->tree_leaf = n_leaf;
+    ctx->have_groups = 0;
+    return SFC_OK;
+}
+
+int tree_refit_hmax(sfc_ctx *ctx, const sfc_particles *p)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if ((r = check_particles(ctx, p, false))) return r;
+    if (!ctx->tree_leaf) return fail(ctx, SFC_EORDER, "tree_refit_hmax: no tree");
+    PartDev pd = part_dev(p);
+    hipError_t e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "tree_refit_hmax");
+}
+
+static int check_group_params(sfc_ctx *ctx, const sfc_group_params *gp)
+{
+    if (gp->policy != SFC_POLICY_COUNT && gp->policy != SFC_POLICY_PAPER)
+        return fail(ctx, SFC_EINVAL, "group params: bad policy %d", gp->policy);
+    if (gp->n_group_max < 1 || gp->n_group_max > SFC_WAVE_GROUP_MAX)
+        return fail(ctx, SFC_EINVAL, "group params: n_group_max %d outside [1, 64]", gp->n_group_max);
+    if (gp->policy == SFC_POLICY_PAPER && !(gp->f >= 0.0))
+        return fail(ctx, SFC_EINVAL, "group params: f must be >= 0");
+    if (gp->chunk < 64) return fail(ctx, SFC_EINVAL, "group params: chunk must be >= 64");
+    return SFC_OK;
+}
+
+static int check_tile(sfc_ctx *ctx, int t_cand)
+{
+    if (t_cand < 64 || t_cand % 64 != 0 || t_cand > ctx->dims.t_cand_max)
+        return fail(ctx, SFC_EINVAL, "t_cand %d must be a multiple of 64 in [64, %d]", t_cand,
+                    ctx->dims.t_cand_max);
+    return SFC_OK;
+}
+
+int group_ngb_search(sfc_ctx *ctx, const sfc_particles *p, const sfc_group_params *gp,
+                     const sfc_group_params *gp_box, const sfc_verify *verify, int32_t t_cand)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if ((r = check_particles(ctx, p, false))) return r;
+    if (!ctx->tree_leaf) return fail(ctx, SFC_EORDER, "group_ngb_search: build the tree first");
+    if (!gp && !gp_box) return fail(ctx, SFC_EINVAL, "group_ngb_search: no group parameters");
+    if (gp && (r = check_group_params(ctx, gp))) return r;
+    if (verify) {
+        if ((r = check_tile(ctx, t_cand))) return r;
+        if (verify->mode != 0 && verify->mode != 1)
+            return fail(ctx, SFC_EINVAL, "verify: mode must be 0 or 1");
+        if (!verify->count) return fail(ctx, SFC_EINVAL, "verify: count is required");
+        if (verify->list && !verify->list_off)
+            return fail(ctx, SFC_EINVAL, "verify: list needs list_off");
+    }
+    PartDev pd = part_dev(p);
+    hipError_t e = launch_groups(ctx->stream, pd, gp_box ? nullptr : gp, gp_box, ctx->gb,
+                                 ctx->scan_tmp, ctx->st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "groups");
+    ctx->gm = gp_box ? SFC_WAVE_GROUP_MAX : gp->n_group_max;
+    ctx->have_groups = 1;
+    if (verify) {
+        e = launch_verify(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, *verify, t_cand, ctx->st,
+                          ctx->gm);
+        if (e != hipSuccess) return hip_fail(ctx, e, "verify");
+    }
+    return SFC_OK;
+}
+
+int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp, sfc_density_out *out)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if ((r = check_particles(ctx, p, true))) return r;
+    if (!dp) return fail(ctx, SFC_EINVAL, "density: params NULL");
+    if (!ctx->have_groups) return fail(ctx, SFC_EORDER, "density: run group_ngb_search first");
+    if (dp->kernel != SFC_KERNEL_CUBIC && dp->kernel != SFC_KERNEL_WC6)
+        return fail(ctx, SFC_EINVAL, "density: bad kernel %d", dp->kernel);
+    if (dp->n_ngb < 1 || dp->dn < 0 || dp->max_iter < 1 || dp->max_iter > 1000)
+        return fail(ctx, SFC_EINVAL, "density: n_ngb >= 1, dn >= 0, 1 <= max_iter <= 1000");
+    if (!(dp->skin >= 1.0 && dp->skin <= 4.0))
+        return fail(ctx, SFC_EINVAL, "density: skin must be in [1, 4]");
+    if (dp->accum != SFC_ACCUM_F32 && dp->accum != SFC_ACCUM_F64)
+        return fail(ctx, SFC_EINVAL, "density: bad accum");
+    if ((r = check_tile(ctx, dp->t_cand))) return r;
+    DensityArgs a;
+    a.dp = *dp;
+    if (out) a.out = *out;
+    else memset(&a.out, 0, sizeof(a.out));
+    PartDev pd = part_dev(p);
+    hipError_t e = launch_density(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st, ctx->gm);
+    if (e != hipSuccess) return hip_fail(ctx, e, "density");
+    // the hydro walk reads every node's max h: refresh it
+    e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "density refit");
+}
+
+int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp,
+                sfc_hydro_out *out)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if ((r = check_particles(ctx, p, true))) return r;
+    if (!hp || !out) return fail(ctx, SFC_EINVAL, "hydro_force: params and out are required");
+    if (!p->vx || !p->vy || !p->vz || !p->u)
+        return fail(ctx, SFC_EINVAL, "hydro_force: vx, vy, vz, u are required");
+    if (!out->ax || !out->ay || !out->az || !out->dudt || !out->vsigmax)
+        return fail(ctx, SFC_EINVAL, "hydro_force: ax, ay, az, dudt, vsigmax are required");
+    if (!ctx->have_groups) return fail(ctx, SFC_EORDER, "hydro_force: run group_ngb_search first");
+    if (hp->kernel != SFC_KERNEL_CUBIC && hp->kernel != SFC_KERNEL_WC6)
+        return fail(ctx, SFC_EINVAL, "hydro_force: bad kernel %d", hp->kernel);
+    if (!(hp->gamma > 1.0) || !(hp->alpha >= 0.0))
+        return fail(ctx, SFC_EINVAL, "hydro_force: gamma > 1 and alpha >= 0 required");
+    if (hp->accum != SFC_ACCUM_F32 && hp->accum != SFC_ACCUM_F64)
+        return fail(ctx, SFC_EINVAL, "hydro_force: bad accum");
+    if ((r = check_tile(ctx, hp->t_cand))) return r;
+    HydroArgs a;
+    a.hp = *hp;
+    a.out = *out;
+    PartDev pd = part_dev(p);
+    hipError_t e = launch_hydro(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st, ctx->gm);
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "hydro_force");
+}
+
+int sfc_status_read(sfc_ctx *ctx, sfc_status *out)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if (!out) return fail(ctx, SFC_EINVAL, "status: out NULL");
+    DevStatus s;
+    hipError_t e = hipMemcpyAsync(&s, ctx->st, sizeof(s), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "status read");
+    out->flags = s.flags;
+    out->n_nodes = s.n_nodes;
+    out->n_active = s.n_active;
+    out->n_groups = s.n_groups;
+    out->n_deferred = (int64_t)s.n_deferred;
+    out->n_overflow = (int64_t)s.n_overflow;
+    out->n_not_converged = (int64_t)s.n_not_converged;
+    out->sum_cand = (int64_t)s.sum_cand;
+    out->n_walks = (int64_t)s.n_walks;
+    out->sum_iters = (int64_t)s.sum_iters;
+    if (s.flags & (SFC_ST_LIST_OVERFLOW | SFC_ST_NODE_OVERFLOW | SFC_ST_GUARD))
+        return fail(ctx, SFC_EOVERFLOW, "device capacity or loop limit exceeded (flags 0x%x)", s.flags);
+    return SFC_OK;
+}
+
+int sfc_get_views(const sfc_ctx *ctx, sfc_views *out)
+{
+    if (!ctx || !out) return SFC_EINVAL;
+    if (!ctx->bound) return SFC_EWORKSPACE;
+    out->capacity = ctx->td.capacity;
+    out->n_nodes = &ctx->st->n_nodes;
+    out->info = (const int32_t *)ctx->td.info;
+    out->lo = (const double *)ctx->td.lo;
+    out->hi = (const double *)ctx->td.hi;
+    out->box_root = ctx->td.box_root;
+    out->act = ctx->gb.act;
+    out->n_act = ctx->gb.n_act;
+    out->goff = ctx->gb.goff;
+    out->n_groups = ctx->gb.n_groups;
+    return SFC_OK;
+}
+
+int sfc_graph_begin(sfc_ctx *ctx)
+{
+    if (!ctx) return SFC_EINVAL;
+    if (!ctx->stream) return fail(ctx, SFC_EINVAL, "graph capture needs a non-null stream");
+    hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(ctx, e, "begin capture");
+    ctx->capturing = true;
+    return SFC_OK;
+}
+
+int sfc_graph_end(sfc_ctx *ctx, sfc_graph **out)
+{
+    if (!ctx || !out) return SFC_EINVAL;
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+    ctx->capturing = false;
+    if (e != hipSuccess) return hip_fail(ctx, e, "end capture");
+    sfc_graph *sg = new (std::nothrow) sfc_graph();
+    if (!sg) {
+        (void)hipGraphDestroy(g);
+        return fail(ctx, SFC_EINVAL, "graph: out of host memory");
+    }
+    sg->g = g;
+    e = hipGraphInstantiate(&sg->e, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete sg;
+        return hip_fail(ctx, e, "graph instantiate");
+    }
+    *out = sg;
+    return SFC_OK;
+}
+
+int sfc_graph_launch(sfc_ctx *ctx, sfc_graph *g)
+{
+    if (!ctx || !g) return SFC_EINVAL;
+    hipError_t e = hipGraphLaunch(g->e, ctx->stream);
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "graph launch");
+}
+
+void sfc_graph_destroy(sfc_graph *g)
+{
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->e);
+    (void)hipGraphDestroy(g->g);
+    delete g;
+}
+
+} // extern "C"

@@ -1,0 +1,232 @@
+// internal.h -- shared device helpers and workspace views of the sfcngb
+// library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sfcngb.h"
+
+#define SFC_KEY_BITS 21
+#define SFC_WG 256 // threads per workgroup in the persistent kernels (4 waves)
+
+// ---------------------------------------------------------------- wave ops
+__device__ __forceinline__ int lane_id()
+{
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// number of set bits of m below this lane
+__device__ __forceinline__ int mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ int popc64(uint64_t m) { return __builtin_popcountll(m); }
+__device__ __forceinline__ int ctz64(uint64_t m) { return m ? __builtin_ctzll(m) : 64; }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    union { double d; int i[2]; } a, b;
+    a.d = v;
+    b.i[0] = __builtin_amdgcn_readlane(a.i[0], l);
+    b.i[1] = __builtin_amdgcn_readlane(a.i[1], l);
+    return b.d;
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+// write the uniform value s into lane l of v
+__device__ __forceinline__ uint64_t writelane_u64(uint64_t v, uint64_t s, int l)
+{
+    return lane_id() == l ? s : v;
+}
+// order LDS accesses of the lanes of one wave (each wave owns its LDS slice)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max_f(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_sum_f_or_d(float v) { return wave_sum_f(v); }
+__device__ __forceinline__ double wave_sum_f_or_d(double v) { return wave_sum_d(v); }
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t lo = __shfl_xor((unsigned)(uint32_t)v, o, 64);
+        uint32_t hi = __shfl_xor((unsigned)(uint32_t)(v >> 32), o, 64);
+        v += ((uint64_t)hi << 32) | lo;
+    }
+    return v;
+}
+
+// ------------------------------------------------------- box helpers
+// box b with box_off[b] <= i < box_off[b+1] (boxes may be empty)
+__device__ __forceinline__ int box_of(const int64_t *box_off, int nb, int64_t i)
+{
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (box_off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// minimum-image fold of a coordinate difference into [-L/2, L/2)
+__device__ __forceinline__ double fold(double d, double L)
+{
+    double half = 0.5 * L;
+    if (d >= half) d = d - L;
+    else if (d < -half) d = d + L;
+    return d;
+}
+
+// ------------------------------------------------------- status block
+struct DevStatus {
+    uint32_t flags;
+    int32_t n_nodes;
+    int32_t n_active;
+    int32_t n_groups;
+    unsigned long long n_deferred;
+    unsigned long long n_overflow;
+    unsigned long long n_not_converged;
+    unsigned long long sum_cand;
+    unsigned long long n_walks;
+    unsigned long long sum_iters;
+    int32_t queue_head[4]; // work-queue heads of the persistent kernels
+    int32_t n_defer_list;  // length of the deferred-member list
+    int32_t pad[3];
+};
+
+// ------------------------------------------------------- tree view
+struct TreeDev {
+    int4 *info;     // first, count, skip, level | leaf << 8
+    double4 *lo;    // min x, min y, min z, hmax
+    double4 *hi;    // max x, max y, max z, 0
+    int32_t *parent;
+    int32_t *nchild;
+    int32_t *counter;
+    int32_t *box_root; // [nb+1]
+    int32_t capacity;
+};
+
+// ------------------------------------------------------- particle view
+struct PartDev {
+    int64_t n;
+    int nb;
+    const int64_t *box_off;
+    const double *box_L;
+    const double *x, *y, *z;
+    double *h;
+    const float *m, *vx, *vy, *vz, *u;
+    float *rho, *fgrad;
+    const uint8_t *active;
+    const uint32_t *orig;
+};
+
+// splitmix64 finaliser (Steele, Lea, Flood 2014) for neighbour fingerprints
+__device__ __forceinline__ uint64_t mix64(uint64_t v)
+{
+    v += 0x9e3779b97f4a7c15ull;
+    v = (v ^ (v >> 30)) * 0xbf58476d1ce4e5b9ull;
+    v = (v ^ (v >> 27)) * 0x94d049bb133111ebull;
+    return v ^ (v >> 31);
+}
+
+// ------------------------------------------------------- host-side launchers
+// (defined in the .hip files, called by the C-ABI layer)
+struct SortBufs {
+    uint64_t *key_a, *key_b;
+    uint32_t *val_a, *val_b;
+    uint32_t *box_a, *box_b; // box ids (batched sort only)
+    uint32_t *hist;          // 256 * ntiles
+    uint32_t *scan_tmp;      // scratch for the device scan
+};
+
+hipError_t launch_keys(hipStream_t s, const sfc_particles *in, SortBufs &b);
+hipError_t launch_radix_sort(hipStream_t s, int64_t n, int nb, SortBufs &b, uint64_t *keys_out,
+                             uint32_t **perm_out);
+hipError_t launch_gather(hipStream_t s, const sfc_particles *in, sfc_particles *out,
+                         const uint32_t *perm, uint32_t *perm_out);
+size_t scan_tmp_elems(int64_t n);
+hipError_t launch_scan_excl_u32(hipStream_t s, const uint32_t *in, uint32_t *out, int64_t n,
+                                uint32_t *tmp, uint32_t *total);
+hipError_t launch_fill_i32(hipStream_t s, int32_t *p, int32_t v, int64_t n);
+
+struct TreeBufs {
+    int8_t *lcp;     // [n]
+    int8_t *dlev;    // [n]
+    uint32_t *cnt;   // [n+1]
+    uint32_t *start; // [n+1]
+};
+hipError_t launch_tree_build(hipStream_t s, const PartDev &p, const uint64_t *keys, int n_leaf,
+                             TreeBufs &tb, TreeDev &t, uint32_t *scan_tmp, DevStatus *st);
+hipError_t launch_tree_refit(hipStream_t s, const PartDev &p, TreeDev &t, bool bbox,
+                             DevStatus *st, int64_t n);
+
+struct GroupBufs {
+    uint32_t *flag_scan; // [n+1] exclusive scan of active flags
+    int32_t *act;        // [n]
+    int32_t *chunk_base; // [nb+1]
+    int32_t *gs_local;   // [n] group starts per chunk (chunk-local slots)
+    uint32_t *gcount;    // [max_chunks+1]
+    uint32_t *gscan;     // [max_chunks+1]
+    int32_t *goff;       // [n+1]
+    int32_t *n_act;      // device scalar
+    int32_t *n_groups;   // device scalar
+    int64_t max_chunks;
+};
+hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params *gp,
+                         const sfc_group_params *gp_box, GroupBufs &g, uint32_t *scan_tmp,
+                         DevStatus *st);
+
+struct SearchBufs {
+    double *it_lo, *it_hi; // [n] saved h-bracket of deferred members
+    int32_t *it_n;         // [n] saved evaluation count
+    int32_t *defer;        // [n] deferred member list
+    float *pf, *cs;        // [n] hydro: f P / rho^2 and sound speed per particle
+    int32_t cu_count;
+};
+struct DensityArgs {
+    sfc_density_params dp;
+    sfc_density_out out;
+};
+struct HydroArgs {
+    sfc_hydro_params hp;
+    sfc_hydro_out out;
+};
+hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                          SearchBufs &sb, const DensityArgs &a, DevStatus *st, int gm);
+hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                        SearchBufs &sb, const HydroArgs &a, DevStatus *st, int gm);
+hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st, int gm);

@@ -1,0 +1,263 @@
+// tree.hip -- octree over Hilbert-sorted particles.
+//
+// Node = non-empty Hilbert cell.  With keys sorted, the cell of level l that
+// holds particle i starts where the level-l key prefix changes.  Two
+// per-particle numbers give the whole tree without recursion:
+//   lcp(i)  levels shared by key[i-1] and key[i] (-1 at a box start): the
+//           cells starting at i are those of level > lcp(i);
+//   d(i)    deepest level whose cell around i holds more than n_leaf
+//           particles = max over the windows [s, s+n_leaf] that contain i of
+//           the levels shared by key[s] and key[s+n_leaf].
+// Nodes starting at i are the levels lcp(i)+1 .. min(21, d(i)+1); the last
+// one is a leaf.  Emitting them for every i in order, levels ascending, is a
+// depth-first pre-order of the octree, so an exclusive scan of the counts
+// numbers the nodes, a node's first child is the next node and its skip link
+// is the first node starting at the end of its cell.  Bounding boxes and
+// max(h) are reduced from the leaves to the root with per-node arrival
+// counters (the last child to arrive combines the node).
+#include "internal.h"
+
+__device__ __forceinline__ int common_levels(uint64_t a, uint64_t b)
+{
+    uint64_t x = a ^ b;
+    if (x == 0) return SFC_KEY_BITS;
+    return (__builtin_clzll(x) - 1) / 3; // bit 63 is always clear
+}
+
+__global__ void k_tree_prefix(int64_t n, int nb, const int64_t *__restrict__ box_off,
+                              const uint64_t *__restrict__ key, int n_leaf,
+                              int8_t *__restrict__ lcp, int8_t *__restrict__ cwin)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = nb > 1 ? box_of(box_off, nb, i) : 0;
+    int64_t bs = box_off[b], be = box_off[b + 1];
+    uint64_t k = key[i];
+    lcp[i] = (int8_t)(i == bs ? -1 : common_levels(key[i - 1], k));
+    cwin[i] = (int8_t)(i + n_leaf < be ? common_levels(k, key[i + n_leaf]) : -1);
+}
+
+__global__ void k_tree_count(int64_t n, int nb, const int64_t *__restrict__ box_off,
+                             int n_leaf, const int8_t *__restrict__ lcp,
+                             const int8_t *__restrict__ cwin, int8_t *__restrict__ dlev,
+                             uint32_t *__restrict__ cnt)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        cnt[n] = 0;
+        return;
+    }
+    int b = nb > 1 ? box_of(box_off, nb, i) : 0;
+    int64_t bs = box_off[b];
+    int64_t s0 = i - n_leaf > bs ? i - n_leaf : bs;
+    int d = -1;
+    for (int64_t s = s0; s <= i; s++) d = max(d, (int)cwin[s]);
+    dlev[i] = (int8_t)d;
+    int lo = lcp[i] + 1;
+    int hi = min(SFC_KEY_BITS, d + 1);
+    cnt[i] = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+}
+
+// first index in (i, be) whose key differs from key[i] above bit `sh`
+__device__ __forceinline__ int64_t cell_end(const uint64_t *key, int64_t i, int64_t be, int sh)
+{
+    uint64_t pref = key[i] >> sh;
+    int64_t good = i, step = 1, probe = i + 1;
+    while (probe < be && (key[probe] >> sh) == pref) {
+        good = probe;
+        step <<= 1;
+        probe = i + step;
+    }
+    int64_t bad = probe < be ? probe : be; // key[bad] differs or bad == be
+    while (bad - good > 1) {
+        int64_t mid = good + ((bad - good) >> 1);
+        if ((key[mid] >> sh) == pref) good = mid; else bad = mid;
+    }
+    return bad;
+}
+
+// first index in [bs, i] whose key shares key[i]'s prefix above bit `sh`
+__device__ __forceinline__ int64_t cell_begin(const uint64_t *key, int64_t bs, int64_t i, int sh)
+{
+    uint64_t pref = key[i] >> sh;
+    int64_t lo = bs - 1, hi = i; // key[hi] matches; key[lo] differs (or lo < bs)
+    while (hi - lo > 1) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if ((key[mid] >> sh) == pref) hi = mid; else lo = mid;
+    }
+    return hi;
+}
+
+__global__ void k_tree_emit(int64_t n, int nb, const int64_t *__restrict__ box_off,
+                            const uint64_t *__restrict__ key, const int8_t *__restrict__ lcp,
+                            const int8_t *__restrict__ dlev, const uint32_t *__restrict__ start,
+                            TreeDev t, DevStatus *st)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = lcp[i] + 1;
+    int hi = min(SFC_KEY_BITS, (int)dlev[i] + 1);
+    if (hi < lo) return;
+    int b = nb > 1 ? box_of(box_off, nb, i) : 0;
+    int64_t bs = box_off[b], be = box_off[b + 1];
+    uint32_t base = start[i];
+    for (int l = lo; l <= hi; l++) {
+        int64_t id = (int64_t)base + (l - lo);
+        if (id >= t.capacity) {
+            atomicOr(&st->flags, SFC_ST_NODE_OVERFLOW);
+            return;
+        }
+        int sh = 3 * (SFC_KEY_BITS - l);
+        int64_t end = l == 0 ? be : cell_end(key, i, be, sh);
+        int leaf = l == hi;
+        int4 inf;
+        inf.x = (int)i;
+        inf.y = (int)(end - i);
+        inf.z = (int)start[end];
+        inf.w = l | (leaf << 8);
+        t.info[id] = inf;
+        int par;
+        if (l > lo) {
+            par = (int)id - 1;
+        } else if (l == 0) {
+            par = -1;
+        } else {
+            int64_t p = cell_begin(key, bs, i, sh + 3);
+            par = (int)(start[p] + (uint32_t)((l - 1) - (lcp[p] + 1)));
+        }
+        t.parent[id] = par;
+    }
+}
+
+__global__ void k_tree_roots(int nb, const int64_t *__restrict__ box_off,
+                             const uint32_t *__restrict__ start, int32_t *__restrict__ box_root,
+                             DevStatus *st, int64_t n)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b <= nb) box_root[b] = (int32_t)start[box_off[b]];
+    if (b == 0) st->n_nodes = (int32_t)start[n];
+}
+
+__global__ void k_tree_nchild(const TreeDev t, const DevStatus *st)
+{
+    int id = blockIdx.x * blockDim.x + threadIdx.x;
+    int nn = min(st->n_nodes, t.capacity);
+    if (id >= nn) return;
+    int4 inf = t.info[id];
+    int k = 0;
+    if (!(inf.w >> 8)) {
+        int c = id + 1;
+        int end = min(inf.z, nn);
+        while (c < end) {
+            k++;
+            c = t.info[c].z;
+        }
+    }
+    t.nchild[id] = k;
+    t.counter[id] = 0;
+}
+
+// leaves: reduce their particles; then climb while this thread is the last
+// child to arrive at the parent.
+__global__ void k_tree_up(const PartDev p, const TreeDev t, const DevStatus *st_in,
+                          DevStatus *st, int with_bbox)
+{
+    int id = blockIdx.x * blockDim.x + threadIdx.x;
+    int nn = min(st_in->n_nodes, t.capacity);
+    if (id >= nn) return;
+    int4 inf = t.info[id];
+    if (!(inf.w >> 8)) return;
+    double4 lo = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+    double4 hi = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
+    double hm = 0.0;
+    int bad = 0;
+    int b = p.nb > 1 ? box_of(p.box_off, p.nb, inf.x) : 0;
+    double L = p.box_L[b];
+    for (int i = inf.x; i < inf.x + inf.y; i++) {
+        double hh = p.h[i];
+        hm = fmax(hm, hh);
+        bad |= !(hh > 0.0);
+        if (with_bbox) {
+            double x = p.x[i], y = p.y[i], z = p.z[i];
+            lo.x = fmin(lo.x, x); hi.x = fmax(hi.x, x);
+            lo.y = fmin(lo.y, y); hi.y = fmax(hi.y, y);
+            lo.z = fmin(lo.z, z); hi.z = fmax(hi.z, z);
+            bad |= !(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L);
+        }
+    }
+    if (bad) atomicOr(&st->flags, SFC_ST_BAD_INPUT);
+    if (with_bbox) {
+        lo.w = hm;
+        t.lo[id] = lo;
+        t.hi[id] = hi;
+    } else {
+        t.lo[id].w = hm;
+    }
+    int k = id;
+    for (;;) {
+        int par = t.parent[k];
+        if (par < 0) break;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        int old = __hip_atomic_fetch_add(&t.counter[par], 1, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+        if (old != t.nchild[par] - 1) break;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        int4 pin = t.info[par];
+        double4 plo = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+        double4 phi = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
+        double phm = 0.0;
+        int cend = min(pin.z, nn);
+        for (int c = par + 1; c < cend; c = t.info[c].z) {
+            double4 clo = t.lo[c];
+            phm = fmax(phm, clo.w);
+            if (with_bbox) {
+                double4 chi = t.hi[c];
+                plo.x = fmin(plo.x, clo.x); plo.y = fmin(plo.y, clo.y); plo.z = fmin(plo.z, clo.z);
+                phi.x = fmax(phi.x, chi.x); phi.y = fmax(phi.y, chi.y); phi.z = fmax(phi.z, chi.z);
+            }
+        }
+        if (with_bbox) {
+            plo.w = phm;
+            t.lo[par] = plo;
+            t.hi[par] = phi;
+        } else {
+            t.lo[par].w = phm;
+        }
+        k = par;
+    }
+}
+
+hipError_t launch_tree_build(hipStream_t s, const PartDev &p, const uint64_t *keys, int n_leaf,
+                             TreeBufs &tb, TreeDev &t, uint32_t *scan_tmp, DevStatus *st)
+{
+    int64_t n = p.n;
+    unsigned gb = (unsigned)((n + 256) / 256);
+    k_tree_prefix<<<gb, 256, 0, s>>>(n, p.nb, p.box_off, keys, n_leaf, tb.lcp, (int8_t *)tb.start);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // cwin lives in the (not yet used) start buffer
+    k_tree_count<<<gb, 256, 0, s>>>(n, p.nb, p.box_off, n_leaf, tb.lcp, (const int8_t *)tb.start,
+                                    tb.dlev, tb.cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = launch_scan_excl_u32(s, tb.cnt, tb.start, n + 1, scan_tmp, nullptr);
+    if (e != hipSuccess) return e;
+    k_tree_emit<<<gb, 256, 0, s>>>(n, p.nb, p.box_off, keys, tb.lcp, tb.dlev, tb.start, t, st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_tree_roots<<<(p.nb + 1 + 255) / 256, 256, 0, s>>>(p.nb, p.box_off, tb.start, t.box_root,
+                                                       st, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_tree_refit(s, p, t, true, st, n);
+}
+
+hipError_t launch_tree_refit(hipStream_t s, const PartDev &p, TreeDev &t, bool bbox,
+                             DevStatus *st, int64_t n)
+{
+    (void)n;
+    unsigned gnodes = (unsigned)((t.capacity + 255) / 256);
+    k_tree_nchild<<<gnodes, 256, 0, s>>>(t, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tree_up<<<gnodes, 256, 0, s>>>(p, t, st, st, bbox ? 1 : 0);
+    return hipGetLastError();
+}
