@@ -118,7 +118,7 @@ def lognormal_positions(rng, n, grid=256, sigma=1.5, slope=-2.0):
     del white
     wk *= amp
     del amp
-    delta = np.fft.irfftn(wk, s=(grid, grid, grid))
+    delta = np.fft.irfftn(wk, s=(grid, grid, grid), axes=(0, 1, 2))
     del wk
     delta *= sigma / delta.std()
     rho = np.exp(delta - 0.5 * sigma * sigma).ravel()
@@ -153,12 +153,14 @@ def initial_h(rng, x, y, z, n_ngb, perturb=0.1, chunk=1 << 18):
     return h, nd
 
 
-def active_cells(rng, x, y, z, fraction, run_mean):
+def active_cells(rng, x, y, z, fraction, run_mean, within=None):
     """Switch on whole level-l cells in random order until `fraction` of the
-    particles are active; l is chosen so a cell holds ~run_mean particles."""
+    particles are active; l is chosen so a cell holds ~run_mean particles.
+    With `within` (a 0/1 mask made by this function with the same run_mean),
+    only cells lying wholly inside it are drawn, so the result is a subset."""
     n = len(x)
     if fraction >= 1.0:
-        return np.ones(n, np.uint8)
+        return np.ones(n, np.uint8) if within is None else within.astype(np.uint8)
     lev = max(1, int(round(math.log(max(n / run_mean, 1.0), 8))))
     g = 1 << lev
     ix = np.minimum((x * g).astype(np.int64), g - 1)
@@ -166,7 +168,10 @@ def active_cells(rng, x, y, z, fraction, run_mean):
     iz = np.minimum((z * g).astype(np.int64), g - 1)
     cid = (ix * g + iy) * g + iz
     cnt = np.bincount(cid, minlength=g ** 3)
-    order = rng.permutation(np.nonzero(cnt)[0])
+    pool = cnt > 0
+    if within is not None:
+        pool &= np.bincount(cid, weights=within, minlength=g ** 3) == cnt
+    order = rng.permutation(np.nonzero(pool)[0])
     csum = np.cumsum(cnt[order])
     take = int(np.searchsorted(csum, fraction * n)) + 1
     on = np.zeros(g ** 3, bool)
@@ -277,7 +282,7 @@ def lognormal_bins(n=16777216, seed=5, grid=256, sigma=1.5, n_ngb=295, dn=6,
     h, nd = initial_h(rng, x, y, z, n_ngb)
     st = _state(x, y, z, h, nd, n, rng=rng, hydro=True)
     b1 = active_cells(rng, x, y, z, 0.10, run_mean)
-    b2 = active_cells(rng, x, y, z, 0.01, run_mean) & b1
+    b2 = active_cells(rng, x, y, z, 0.01, run_mean, within=b1)
     st["bin"] = (b1.astype(np.uint8) + b2.astype(np.uint8))
     st["active"] = np.ones(n, np.uint8)
     off, L = _one_box(n)
