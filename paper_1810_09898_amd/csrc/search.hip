@@ -133,6 +133,34 @@ struct GroupArg {
 
 namespace {
 
+// ------------------------------------------------------------------ scheduling
+// Workgroups are dealt to the 8 XCDs round-robin (block b on XCD b mod 8),
+// and each XCD has its own L2.  Give each XCD one contiguous eighth of the
+// groups (groups follow the Hilbert curve, so an eighth is a compact region
+// of space): the waves on one XCD then share the tree nodes and particles
+// they read.  Within an XCD the waves take the groups in a round-robin
+// stride, so the groups in flight are neighbours.
+struct GroupRange {
+    int g, end, stride;
+};
+__device__ __forceinline__ GroupRange group_range(int G)
+{
+    const int W = (int)gridDim.x;
+    GroupRange r;
+    if (W < 8 || (W & 7)) {
+        r.g = blockIdx.x;
+        r.end = G;
+        r.stride = W;
+        return r;
+    }
+    const int xcd = blockIdx.x & 7;
+    const int gx = (G + 7) >> 3;
+    r.g = xcd * gx + (int)(blockIdx.x >> 3);
+    r.end = min(G, (xcd + 1) * gx);
+    r.stride = W >> 3;
+    return r;
+}
+
 // ------------------------------------------------------------------ walk
 struct Ball {
     double cx, cy, cz, L;
@@ -196,8 +224,30 @@ template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4
     wave_lds_sync();
 }
 
+// inclusive prefix maximum over the lanes of a wave
+__device__ __forceinline__ int wave_incl_max(int v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v = max(v, t);
+    }
+    return v;
+}
+
 // Stackless pre-order walk of nodes [root, root_end): `visit` receives the
 // particles of every opened leaf, in ascending order.
+//
+// The 64 lanes test the 64 consecutive pre-order nodes [k, k+64) at once.
+// The window start is always on the walk (all its ancestors are open).  A
+// closed node c hides its subtree, the node range (c, skip(c)); a node j of
+// the window is on the walk iff no closed node before it in the window hides
+// it, i.e. iff the prefix maximum of the skip links of the closed nodes
+// before j does not exceed j (ancestors before the window are ancestors of
+// the window start, hence open).  The next window starts at the larger of
+// k + 64 and the largest skip link of a closed node in the window: every
+// node in between is hidden.  Each window advances k by at least 64.
 template <class V>
 __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkLds wl, V &visit,
                      DevStatus *st)
@@ -206,15 +256,15 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkL
     int k = uni(root);
     root_end = uni(root_end);
     int steps = 0;
-    const int max_steps = root_end - k + 2; // every step advances k by at least one node
+    const int max_steps = (root_end - k) / 64 + 2;
     while (k < root_end) {
         if (visit.stop()) break;
         if (++steps > max_steps) {
             guard_hit(st);
             break;
         }
-        int node = k + lane;
-        bool inr = node < root_end;
+        const int node = k + lane;
+        const bool inr = node < root_end;
         int4 inf = make_int4(0, 0, 0, 0);
         bool open = false;
         if (inr) {
@@ -227,40 +277,16 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkL
             double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, lo.w)) * INFL) : B.W2;
             open = d2 < lim;
         }
-        const uint64_t O = ballot(open);
-        const uint64_t LF = ballot(inr && (inf.w >> 8));
-        const int nin = root_end - k;
-        const int skr = inf.z - k;
-        uint64_t vis = 0ull;
-        int j = 0, nk = root_end;
-        for (int it = 0; it < 65; it++) { // j strictly increases: at most 64 rounds
-            int run = ctz64((~O) >> j);
-            if (j + run >= 64) {
-                vis |= ~0ull << j;
-                nk = k + 64;
-                break;
-            }
-            vis |= ((1ull << run) - 1ull) << j;
-            j += run;
-            if (j >= nin) {
-                nk = root_end;
-                break;
-            }
-            int sk = uni(readlane_i(skr, j));
-            if (sk >= 64) {
-                nk = k + sk;
-                break;
-            }
-            if (sk <= j) { // a skip link that does not move forward: corrupt tree
-                guard_hit(st);
-                nk = root_end;
-                break;
-            }
-            j = sk;
-        }
-        const uint64_t vl = vis & LF;
+        const int hide = (inr && !open) ? inf.z : -1;
+        const int incl = wave_incl_max(hide);
+        int excl = __shfl_up(incl, 1, 64);
+        if (lane == 0) excl = -1;
+        const bool on_walk = inr && excl <= node;
+        const uint64_t vl = ballot(on_walk && open && (inf.w >> 8));
+        const int far = uni(readlane_i(incl, 63));
+        int nk = max(k + 64, far);
         if (vl) emit_leaves(vl, inf, wl, visit);
-        k = uni(nk);
+        k = uni(min(nk, root_end));
     }
 }
 
@@ -657,7 +683,8 @@ template <int KER, typename ACC> __global__ __launch_bounds__(64) void k_density
     const GroupLds S = carve(lds_raw, k.ga.T, k.ga.gm);
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    const GroupRange gr = group_range(G);
+    for (int g = gr.g; g < gr.end; g += gr.stride) {
         const GroupHead H = group_head(k.g, k.ga, g);
         const double cov = H.R + k.skin * H.H;
         Ball B{H.cx, H.cy, H.cz, H.L, sq(cov * INFL), 0.0, 0.0, 0};
@@ -883,7 +910,8 @@ template <int KER, typename ACC> __global__ __launch_bounds__(64) void k_hydro(H
     const GroupLds S = carve(lds_raw, k.ga.T, k.ga.gm);
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    const GroupRange gr = group_range(G);
+    for (int g = gr.g; g < gr.end; g += gr.stride) {
         const GroupHead H = group_head(k.g, k.ga, g);
         Ball B{H.cx, H.cy, H.cz, H.L, 0.0, H.R, H.H, 1};
         AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, S.cand, k.ga.T, 0, false, false, B, 0.0};
@@ -1028,7 +1056,8 @@ __global__ __launch_bounds__(64) void k_verify(VerK k)
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
     const int mode = k.ver.mode;
-    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+    const GroupRange gr = group_range(G);
+    for (int g = gr.g; g < gr.end; g += gr.stride) {
         const GroupHead H = group_head(k.g, k.ga, g);
         const double cov = H.R + H.H;
         Ball B = mode == 0 ? Ball{H.cx, H.cy, H.cz, H.L, sq(cov * INFL), 0.0, 0.0, 0}
@@ -1109,12 +1138,20 @@ GroupArg make_groups(const GroupBufs &gb, int T, int gm)
     return a;
 }
 
-// waves: enough to fill the chip several times over, never more than groups
-int64_t wave_count(int cu, int64_t max_groups)
+// waves: as many as fit on the chip at once (a multiple of 8, one per
+// workgroup), so that every wave is resident and keeps its XCD's groups
+template <class Kern>
+int64_t wave_count(Kern kern, size_t lds, int cu, int64_t max_groups)
 {
-    int64_t w = (int64_t)cu * 16;
-    if (max_groups < w) w = max_groups;
-    return w < 1 ? 1 : w;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 8;
+    int64_t w = (int64_t)cu * per_cu;
+    int64_t cap = ((max_groups + 7) / 8) * 8;
+    if (cap < w) w = cap;
+    w = (w / 8) * 8;
+    return w < 8 ? 8 : w;
 }
 
 template <class Kern, class Arg>
@@ -1125,7 +1162,7 @@ hipError_t launch_waves(Kern kern, hipStream_t s, const Arg &a, size_t lds, int 
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    kern<<<(unsigned)wave_count(cu, max_groups), 64, lds, s>>>(a);
+    kern<<<(unsigned)wave_count(kern, lds, cu, max_groups), 64, lds, s>>>(a);
     return hipGetLastError();
 }
 } // namespace
