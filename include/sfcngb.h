@@ -70,14 +70,19 @@ typedef struct {
     int32_t n_boxes;     /* >= 1 */
     int32_t n_leaf_min;  /* smallest leaf size tree_build will be given (>= 1) */
     int32_t t_cand_max;  /* largest candidate tile any call will use (64..8192, multiple of 64) */
+    int32_t cand_per_particle; /* capacity of the candidate buffer that holds every group's
+                                  superset, in candidates per particle (0 = 64; 1..4096).
+                                  Groups that do not fit finish member by member (slower,
+                                  same results) and are counted in sfc_status.n_overflow. */
 } sfc_dims;
 
 /* Bytes of device workspace needed for `dims` (0 on invalid dims). */
 SFC_API size_t sfc_workspace_bytes(const sfc_dims *dims);
 /* Bind a caller-owned device workspace of ws_bytes >= sfc_workspace_bytes(dims)
  * to the context and clear its status block.  The workspace holds the sort
- * buffers, the octree, the active list and groups, per-particle iteration
- * state and the status block; it must stay alive while the context uses it. */
+ * buffers, the octree, the active list and groups, the candidate supersets
+ * of the groups, per-particle hydro records and the status block; it must
+ * stay alive while the context uses it. */
 SFC_API int sfc_workspace_bind(sfc_ctx *ctx, const sfc_dims *dims, void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------------- */

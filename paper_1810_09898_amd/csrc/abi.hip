@@ -9,11 +9,11 @@
 hipError_t launch_gather(hipStream_t s, const sfc_particles *in, sfc_particles *out,
                          const uint32_t *perm, uint32_t *perm_out);
 hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                          SearchBufs &sb, const DensityArgs &a, DevStatus *st, int gm);
+                          SearchBufs &sb, const DensityArgs &a, DevStatus *st);
 hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                        SearchBufs &sb, const HydroArgs &a, DevStatus *st, int gm);
+                        SearchBufs &sb, const HydroArgs &a, DevStatus *st);
 hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st, int gm);
+                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st);
 
 struct sfc_ctx {
     hipStream_t stream;
@@ -33,7 +33,6 @@ struct sfc_ctx {
     uint32_t *scan_tmp;
     int tree_leaf; // n_leaf of the last tree, 0 = none
     int have_groups;
-    int gm;        // max members of the current groups
     bool capturing;
 };
 
@@ -82,11 +81,20 @@ int64_t max_chunks(const sfc_dims &d) { return d.n / 64 + d.n_boxes + 1; }
 
 int64_t sort_tiles(const sfc_dims &d) { return (d.n + 4095) / 4096; }
 
+int64_t cand_capacity(const sfc_dims &d)
+{
+    int64_t per = d.cand_per_particle > 0 ? d.cand_per_particle : 64;
+    int64_t c = per * d.n + 64 * (int64_t)d.t_cand_max;
+    const int64_t lim = ((int64_t)1 << 31) - 1;
+    return c < lim ? c : lim;
+}
+
 bool dims_ok(const sfc_dims *d)
 {
     return d && d->n >= 1 && d->n < ((int64_t)1 << 30) && d->n_boxes >= 1 &&
            d->n_boxes <= 65536 && d->n_boxes <= d->n && d->n_leaf_min >= 1 &&
            d->t_cand_max >= 64 && d->t_cand_max <= 8192 && d->t_cand_max % 64 == 0 &&
+           d->cand_per_particle >= 0 && d->cand_per_particle <= 4096 &&
            node_capacity(*d) < ((int64_t)1 << 31) - 1;
 }
 
@@ -135,12 +143,12 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     gb.n_groups = b.take<int32_t>(1);
     gb.max_chunks = mc;
     SearchBufs xb;
-    xb.it_lo = b.take<double>(n);
-    xb.it_hi = b.take<double>(n);
-    xb.it_n = b.take<int32_t>(n);
-    xb.defer = b.take<int32_t>(n);
-    xb.pf = b.take<float>(n);
-    xb.cs = b.take<float>(n);
+    xb.cand_cap = cand_capacity(d);
+    xb.cand = b.take<int32_t>(xb.cand_cap);
+    xb.sup = b.take<GSup>(n);
+    xb.grp = b.take<int32_t>(n);
+    xb.pa = b.take<float4>(n);
+    xb.pb = b.take<float4>(n);
     xb.cu_count = c ? c->cu : 0;
     if (c && base) {
         c->st = st;
@@ -366,11 +374,9 @@ int group_ngb_search(sfc_ctx *ctx, const sfc_particles *p, const sfc_group_param
     hipError_t e = launch_groups(ctx->stream, pd, gp_box ? nullptr : gp, gp_box, ctx->gb,
                                  ctx->scan_tmp, ctx->st);
     if (e != hipSuccess) return hip_fail(ctx, e, "groups");
-    ctx->gm = gp_box ? SFC_WAVE_GROUP_MAX : gp->n_group_max;
     ctx->have_groups = 1;
     if (verify) {
-        e = launch_verify(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, *verify, t_cand, ctx->st,
-                          ctx->gm);
+        e = launch_verify(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, *verify, t_cand, ctx->st);
         if (e != hipSuccess) return hip_fail(ctx, e, "verify");
     }
     return SFC_OK;
@@ -397,7 +403,7 @@ int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp, sfc_de
     if (out) a.out = *out;
     else memset(&a.out, 0, sizeof(a.out));
     PartDev pd = part_dev(p);
-    hipError_t e = launch_density(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st, ctx->gm);
+    hipError_t e = launch_density(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
     if (e != hipSuccess) return hip_fail(ctx, e, "density");
     // the hydro walk reads every node's max h: refresh it
     e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
@@ -427,7 +433,7 @@ int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp
     a.hp = *hp;
     a.out = *out;
     PartDev pd = part_dev(p);
-    hipError_t e = launch_hydro(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st, ctx->gm);
+    hipError_t e = launch_hydro(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
     return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "hydro_force");
 }
 

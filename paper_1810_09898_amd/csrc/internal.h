@@ -122,9 +122,19 @@ struct DevStatus {
     unsigned long long sum_cand;
     unsigned long long n_walks;
     unsigned long long sum_iters;
-    int32_t queue_head[4]; // work-queue heads of the persistent kernels
-    int32_t n_defer_list;  // length of the deferred-member list
-    int32_t pad[3];
+    unsigned long long cand_top; // bump pointer of the candidate buffer (per walk launch)
+    int32_t pad[6];
+};
+
+// per-group record written by the walk kernel
+#define GSUP_WRAP 1 // pairs of this group need the periodic fold
+#define GSUP_SOLO 2 // superset not kept (tile or buffer overflow): members walk alone
+struct GSup {
+    double cx, cy, cz; // centre: the group's first member
+    double cov;        // walk radius (density: R_g + skin * max member h)
+    int64_t c0;        // first candidate in the candidate buffer
+    int32_t nc;        // number of candidates
+    int32_t flags;
 };
 
 // ------------------------------------------------------- tree view
@@ -210,10 +220,11 @@ hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params
                          DevStatus *st);
 
 struct SearchBufs {
-    double *it_lo, *it_hi; // [n] saved h-bracket of deferred members
-    int32_t *it_n;         // [n] saved evaluation count
-    int32_t *defer;        // [n] deferred member list
-    float *pf, *cs;        // [n] hydro: f P / rho^2 and sound speed per particle
+    int32_t *cand;    // [cand_cap] candidate supersets of all groups
+    int64_t cand_cap;
+    GSup *sup;        // [n] per group
+    int32_t *grp;     // [n] per active: its group
+    float4 *pa, *pb;  // [n] hydro records: (m, v) and (rho, f P / rho^2, c, h)
     int32_t cu_count;
 };
 struct DensityArgs {
@@ -225,8 +236,8 @@ struct HydroArgs {
     sfc_hydro_out out;
 };
 hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                          SearchBufs &sb, const DensityArgs &a, DevStatus *st, int gm);
+                          SearchBufs &sb, const DensityArgs &a, DevStatus *st);
 hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                        SearchBufs &sb, const HydroArgs &a, DevStatus *st, int gm);
+                        SearchBufs &sb, const HydroArgs &a, DevStatus *st);
 hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st, int gm);
+                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st);

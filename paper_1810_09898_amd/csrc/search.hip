@@ -1,27 +1,30 @@
 // search.hip -- grouped neighbour search, density and hydro force.
 //
-// One wavefront owns one group (groups are dealt to waves round-robin).  A
-// group is a run of actives along the Hilbert curve (section
-// "Implementation of Neighbour Recycling using a Space Filling Curve"):
-//   1. walk: the 64 lanes test 64 consecutive pre-order nodes at once and
-//      follow the stackless walk inside that window with ballot masks; the
-//      particles of the opened leaves are tested against the group ball
-//      (centre = first member, radius = R_g + skin*max h for density,
-//      R_g + max(max h, h_j) for hydro) and compacted into an LDS list, in
-//      ascending particle order: the group's candidate superset;
-//   2. filter: lanes hold candidates, the loop runs over members; one FP64
-//      test per (member, candidate) and one ballot give each member a 64-bit
-//      neighbour mask per candidate chunk (kept in LDS);
-//   3. density only: each member iterates its h on the superset while
-//      h + |x_i - x_0| stays inside the walk radius;
-//   4. sums: per member, the masks are compacted (mbcnt) into a FIFO of
-//      neighbour indices; the k-th neighbour always lands on lane k mod 64,
-//      so each lane accumulates a fixed subsequence in a fixed order and the
-//      result does not depend on the group the particle was in.
-// Members whose h outgrows the superset, and all members of a group whose
-// superset overflows the LDS tile, finish alone in the same wave: one walk
-// per h evaluation with the particle's own radius, neighbours streamed
-// through the FIFO.
+// A group is a run of active particles along the Hilbert curve (section
+// "Implementation of Neighbour Recycling using a Space Filling Curve").
+// Every pass (density, hydro, verify) is two kernels:
+//
+//  k_walk: one wavefront per group walks the octree ONCE with the group
+//    ball (centre = first member, radius = R_g + skin * max h for density,
+//    R_g + max(max h, h_j) for hydro).  The 64 lanes test 64 consecutive
+//    pre-order nodes at a time; particles of opened leaves are tested
+//    against the ball and compacted into an LDS tile in ascending order:
+//    the group's candidate superset.  The tile is copied to a global
+//    candidate buffer (bump-allocated) and a per-group record is written.
+//
+//  k_density / k_hydro / k_verify: one wavefront per active particle.  The
+//    lanes hold 64 candidates of the particle's group at a time; one FP64
+//    test each gives the neighbour mask of that chunk.  Density iterates h
+//    on the superset while h + |x_i - x_0| stays inside the walk radius
+//    (masks of the last evaluation are kept in LDS), then streams the
+//    neighbours through an LDS FIFO in which the k-th neighbour always lands
+//    on lane k mod 64: each lane accumulates a fixed subsequence in a fixed
+//    order, so the sums do not depend on the group the particle was in.
+//
+// A particle whose h outgrows the superset, and every member of a group
+// whose superset overflows the tile or the candidate buffer, finishes alone:
+// one walk per h evaluation with its own radius, neighbours streamed through
+// the same FIFO.
 //
 // Every data-dependent loop has a hard trip limit; hitting one sets
 // SFC_ST_GUARD in the status block instead of spinning.
@@ -127,8 +130,14 @@ struct Geom {
     int nb;
 };
 struct GroupArg {
-    const int32_t *act, *goff, *n_groups;
-    int T, gm;
+    const int32_t *act, *goff, *n_groups, *n_act;
+    int T;
+};
+struct CandArg {
+    int32_t *cand; // global candidate buffer
+    int64_t cap;   // its capacity
+    GSup *sup;     // per group
+    int32_t *grp;  // per active: its group
 };
 
 namespace {
@@ -136,28 +145,31 @@ namespace {
 // ------------------------------------------------------------------ scheduling
 // Workgroups are dealt to the 8 XCDs round-robin (block b on XCD b mod 8),
 // and each XCD has its own L2.  Give each XCD one contiguous eighth of the
-// groups (groups follow the Hilbert curve, so an eighth is a compact region
-// of space): the waves on one XCD then share the tree nodes and particles
-// they read.  Within an XCD the waves take the groups in a round-robin
-// stride, so the groups in flight are neighbours.
-struct GroupRange {
-    int g, end, stride;
+// work items (groups or actives, both in Hilbert order, so an eighth is a
+// compact region of space): the waves on one XCD then share the tree nodes
+// and particles they read.  Within an XCD the waves take the items in a
+// round-robin stride, so the items in flight are neighbours, and the waves of
+// one workgroup (one CU) take consecutive items.
+struct ItemRange {
+    int i, end, stride;
 };
-__device__ __forceinline__ GroupRange group_range(int G)
+__device__ __forceinline__ ItemRange item_range(int n_items)
 {
-    const int W = (int)gridDim.x;
-    GroupRange r;
-    if (W < 8 || (W & 7)) {
-        r.g = blockIdx.x;
-        r.end = G;
-        r.stride = W;
+    const int wpg = (int)(blockDim.x >> 6);
+    const int wave = uni((int)(threadIdx.x >> 6));
+    const int nblk = (int)gridDim.x;
+    ItemRange r;
+    if (nblk < 8 || (nblk & 7)) {
+        r.i = (int)blockIdx.x * wpg + wave;
+        r.end = n_items;
+        r.stride = nblk * wpg;
         return r;
     }
     const int xcd = blockIdx.x & 7;
-    const int gx = (G + 7) >> 3;
-    r.g = xcd * gx + (int)(blockIdx.x >> 3);
-    r.end = min(G, (xcd + 1) * gx);
-    r.stride = W >> 3;
+    const int per = (n_items + 7) >> 3;
+    r.i = xcd * per + (int)(blockIdx.x >> 3) * wpg + wave;
+    r.end = min(n_items, (xcd + 1) * per);
+    r.stride = (nblk >> 3) * wpg;
     return r;
 }
 
@@ -290,37 +302,6 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkL
     }
 }
 
-// ------------------------------------------------------------------ LDS
-struct GroupLds {
-    int *cand;       // [T]
-    uint64_t *masks; // [T/64 * gm]
-    double *mx, *my, *mz, *mh; // [64]
-    int *mi;         // [64]
-    WalkLds wl;
-    int *pend;       // [128]
-};
-
-__host__ __device__ constexpr size_t group_lds_bytes(int T, int gm)
-{
-    return (size_t)4 * T + (size_t)8 * (T / 64) * gm + 4 * 64 * 8 + 64 * 4 + (64 + 66 + 128) * 4;
-}
-
-__device__ __forceinline__ GroupLds carve(char *base, int T, int gm)
-{
-    GroupLds g;
-    g.cand = (int *)base;
-    g.masks = (uint64_t *)(base + 4 * T);
-    g.mx = (double *)(g.masks + (T / 64) * gm);
-    g.my = g.mx + 64;
-    g.mz = g.my + 64;
-    g.mh = g.mz + 64;
-    g.mi = (int *)(g.mh + 64);
-    g.wl.first = g.mi + 64;
-    g.wl.pref = g.wl.first + 64;
-    g.pend = g.wl.pref + 66;
-    return g;
-}
-
 // canonical squared distance of x_j relative to x_i (fold when `wrap`)
 __device__ __forceinline__ double r2_of(double xj, double yj, double zj, double xi, double yi,
                                         double zi, double L, bool wrap)
@@ -334,9 +315,10 @@ __device__ __forceinline__ double r2_of(double xj, double yj, double zj, double 
     return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
 }
 
-// candidate collection for a group ball; also records whether any kept
-// candidate needed the periodic fold relative to the centre and the largest
-// per-axis displacement of a kept candidate (lane-wise, see pair_wrap)
+// candidate collection for a group ball into an LDS tile; also records
+// whether any kept candidate needed the periodic fold relative to the centre
+// and the largest per-axis displacement of a kept candidate (lane-wise, see
+// pair_wrap)
 struct AppendCand {
     const double *x, *y, *z, *h;
     int *cand;
@@ -373,6 +355,185 @@ struct AppendCand {
     }
 };
 
+// The raw difference x_j - x_i equals its minimum image (no fold needed) for
+// every member i and candidate j when no one needed a fold relative to the
+// centre and the two largest per-axis displacements add up to less than
+// L/2 (with a margin for rounding); otherwise pairs fold.
+__device__ __forceinline__ bool pair_wrap(bool folded, double cand_ext_lane, bool mfold, double mext,
+                                          double L)
+{
+    const double ext = uni_d(wave_max_d(cand_ext_lane));
+    return folded || mfold || !(ext + mext < 0.49 * L);
+}
+
+// box of particle i: side and octree root range
+struct BoxInfo {
+    double L;
+    int root, root_end;
+};
+__device__ __forceinline__ BoxInfo box_info(const Geom &geo, int i)
+{
+    const int b = geo.nb > 1 ? uni(box_of(geo.box_off, geo.nb, i)) : 0;
+    BoxInfo bi;
+    bi.L = uni_d(geo.box_L[b]);
+    bi.root = uni(geo.box_root[b]);
+    bi.root_end = uni(geo.box_root[b + 1]);
+    return bi;
+}
+
+} // namespace
+
+// ================================================================== walk kernel
+struct WalkK {
+    Geom g;
+    GroupArg ga;
+    CandArg ca;
+    DevStatus *st;
+    double skin; // density ball: R_g + skin * max member h
+    int hydro;   // 1: hydro ball R_g + max(max member h, h_j)
+};
+
+__global__ void k_reset_top(DevStatus *st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->cand_top = 0ull;
+}
+
+// One wave per group: the walk, the superset into the global buffer, the
+// group record and the member -> group map.
+__global__ __launch_bounds__(64) void k_walk(WalkK k)
+{
+    extern __shared__ __align__(16) char lds_raw[];
+    const int T = k.ga.T;
+    int *cand = (int *)lds_raw;
+    WalkLds wl{cand + T, cand + T + 64};
+    const int lane = lane_id();
+    const int G = uni(*k.ga.n_groups);
+    const ItemRange gr = item_range(G);
+    for (int g = gr.i; g < gr.end; g += gr.stride) {
+        const int a = uni(k.ga.goff[g]);
+        const int nm = min(uni(k.ga.goff[g + 1]) - a, 64);
+        const bool mem = lane < nm;
+        const int i = mem ? k.ga.act[a + lane] : 0;
+        const int i0 = uni(readlane_i(i, 0));
+        const BoxInfo bx = box_info(k.g, i0);
+        double xi = 0.0, yi = 0.0, zi = 0.0, hi = 0.0;
+        if (mem) {
+            xi = k.g.x[i];
+            yi = k.g.y[i];
+            zi = k.g.z[i];
+            hi = k.g.h[i];
+        }
+        const double cx = uni_d(readlane_d(xi, 0));
+        const double cy = uni_d(readlane_d(yi, 0));
+        const double cz = uni_d(readlane_d(zi, 0));
+        const double rx = xi - cx, ry = yi - cy, rz = zi - cz;
+        const double dx = fold(rx, bx.L), dy = fold(ry, bx.L), dz = fold(rz, bx.L);
+        const bool mfold = ballot(mem && ((dx != rx) | (dy != ry) | (dz != rz))) != 0ull;
+        const double mext =
+            uni_d(wave_max_d(mem ? fmax(fabs(dx), fmax(fabs(dy), fabs(dz))) : 0.0));
+        const double d = mem ? sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx))) : 0.0;
+        const double R = uni_d(wave_max_d(d));
+        const double H = uni_d(wave_max_d(hi));
+        const double cov = k.hydro ? R + H : R + k.skin * H;
+        Ball B{cx, cy, cz, bx.L, sq(cov * INFL), R, H, k.hydro};
+        AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, cand, T, 0, false, false, B, 0.0};
+        walk(k.g, bx.root, bx.root_end, B, wl, ap, k.st);
+        const int nc = uni(ap.n);
+        int flags = 0;
+        int64_t c0 = 0;
+        if (uni_b(ap.over)) {
+            flags = GSUP_SOLO;
+        } else {
+            unsigned long long base = 0ull;
+            if (lane == 0) base = atomicAdd(&k.st->cand_top, (unsigned long long)nc);
+            base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base)) |
+                   ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32)) << 32);
+            if (base + (unsigned long long)nc > (unsigned long long)k.ca.cap) {
+                flags = GSUP_SOLO;
+            } else {
+                c0 = (int64_t)base;
+                wave_lds_sync();
+                for (int s = lane; s < nc; s += 64) k.ca.cand[c0 + s] = cand[s];
+                if (pair_wrap(uni_b(ap.folded), ap.ext, mfold, mext, bx.L)) flags |= GSUP_WRAP;
+            }
+        }
+        if (lane == 0) {
+            GSup sp;
+            sp.cx = cx;
+            sp.cy = cy;
+            sp.cz = cz;
+            sp.cov = cov;
+            sp.c0 = c0;
+            sp.nc = (flags & GSUP_SOLO) ? 0 : nc;
+            sp.flags = flags;
+            k.ca.sup[g] = sp;
+            atomicAdd(&k.st->n_walks, 1ull);
+            atomicAdd(&k.st->sum_cand, (unsigned long long)nc);
+            if (flags & GSUP_SOLO) atomicAdd(&k.st->n_overflow, 1ull);
+        }
+        if (mem) k.ca.grp[a + lane] = g;
+        wave_lds_sync();
+    }
+}
+
+namespace {
+
+// ------------------------------------------------------------------ per-member set-up
+// LDS of one member wave: neighbour masks of the last filter pass, the FIFO
+// and the walk scratch of the solo path
+struct MemLds {
+    uint64_t *masks; // [T/64]
+    int *fifo;       // [128]
+    WalkLds wl;      // [64] + [66]
+};
+__host__ __device__ constexpr size_t mem_lds_bytes(int T)
+{
+    return (size_t)8 * (T / 64) + (size_t)4 * (128 + 64 + 66 + 2);
+}
+__device__ __forceinline__ MemLds mem_carve(char *base, int T)
+{
+    const int wave = uni((int)(threadIdx.x >> 6));
+    char *p = base + (size_t)wave * mem_lds_bytes(T);
+    MemLds m;
+    m.masks = (uint64_t *)p;
+    m.fifo = (int *)(m.masks + T / 64);
+    m.wl.first = m.fifo + 128;
+    m.wl.pref = m.wl.first + 64;
+    return m;
+}
+
+struct Member {
+    int i, g;
+    double xi, yi, zi, h;
+    double d;     // |x_i - x_0|
+    GSup s;
+    BoxInfo bx;
+};
+__device__ __forceinline__ Member member(const Geom &geo, const GroupArg &ga, const CandArg &ca, int a)
+{
+    Member M;
+    M.i = uni(ga.act[a]);
+    M.g = uni(ca.grp[a]);
+    const GSup *sp = ca.sup + M.g;
+    M.s.cx = uni_d(sp->cx);
+    M.s.cy = uni_d(sp->cy);
+    M.s.cz = uni_d(sp->cz);
+    M.s.cov = uni_d(sp->cov);
+    const int64_t c0 = sp->c0;
+    M.s.c0 = ((int64_t)uni((int)(c0 >> 32)) << 32) | (uint32_t)uni((int)(uint32_t)c0);
+    M.s.nc = uni(sp->nc);
+    M.s.flags = uni(sp->flags);
+    M.bx = box_info(geo, M.i);
+    M.xi = uni_d(geo.x[M.i]);
+    M.yi = uni_d(geo.y[M.i]);
+    M.zi = uni_d(geo.z[M.i]);
+    M.h = uni_d(geo.h[M.i]);
+    const double dx = fold(M.xi - M.s.cx, M.bx.L), dy = fold(M.yi - M.s.cy, M.bx.L),
+                 dz = fold(M.zi - M.s.cz, M.bx.L);
+    M.d = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+    return M;
+}
+
 // FIFO of neighbour indices; the k-th pushed index is consumed by lane k%64
 struct Fifo {
     int *buf; // [128]
@@ -380,6 +541,7 @@ struct Fifo {
     template <class F> __device__ __forceinline__ void push(bool hit, int j, F &consume)
     {
         const uint64_t m = ballot(hit);
+        if (!m) return;
         if (hit) buf[np + mbcnt(m)] = j;
         np = uni(np + popc64(m));
         if (np >= 64) {
@@ -406,118 +568,48 @@ struct Fifo {
     }
 };
 
-// ------------------------------------------------------------------ group set-up
-struct GroupHead {
-    int nm;          // members act[a .. a+nm)
-    int i;           // this lane's member particle (lane < nm)
-    bool mem;
-    double xi, yi, zi, h;
-    double cx, cy, cz, L;
-    double d;        // |x_i - x_0|
-    double R, H;     // max member distance, max member h
-    bool mfold;      // some member needed the periodic fold
-    double mext;     // largest per-axis |x_i - x_0| over members
-    int root, root_end;
-};
-
-// The raw difference x_j - x_i equals its minimum image (no fold needed) for
-// every member i and candidate j when no one needed a fold relative to the
-// centre and the two largest per-axis displacements add up to less than
-// L/2 (with a margin for rounding); otherwise pairs fold.
-__device__ __forceinline__ bool pair_wrap(bool folded, double cand_ext_lane, bool mfold, double mext,
-                                          double L)
-{
-    const double ext = uni_d(wave_max_d(cand_ext_lane));
-    return folded || mfold || !(ext + mext < 0.49 * L);
-}
-
-__device__ __forceinline__ GroupHead group_head(const Geom &geo, const GroupArg &ga, int g)
-{
-    GroupHead G;
-    const int lane = lane_id();
-    const int a = uni(ga.goff[g]);
-    G.nm = min(uni(ga.goff[g + 1]) - a, 64);
-    G.mem = lane < G.nm;
-    G.i = G.mem ? ga.act[a + lane] : 0;
-    const int i0 = uni(readlane_i(G.i, 0));
-    const int b = geo.nb > 1 ? uni(box_of(geo.box_off, geo.nb, i0)) : 0;
-    G.L = uni_d(geo.box_L[b]);
-    G.root = uni(geo.box_root[b]);
-    G.root_end = uni(geo.box_root[b + 1]);
-    G.xi = G.yi = G.zi = G.h = 0.0;
-    if (G.mem) {
-        G.xi = geo.x[G.i];
-        G.yi = geo.y[G.i];
-        G.zi = geo.z[G.i];
-        G.h = geo.h[G.i];
-    }
-    G.cx = uni_d(readlane_d(G.xi, 0));
-    G.cy = uni_d(readlane_d(G.yi, 0));
-    G.cz = uni_d(readlane_d(G.zi, 0));
-    double rx = G.xi - G.cx, ry = G.yi - G.cy, rz = G.zi - G.cz;
-    double dx = fold(rx, G.L), dy = fold(ry, G.L), dz = fold(rz, G.L);
-    bool fl = G.mem && ((dx != rx) | (dy != ry) | (dz != rz));
-    G.mfold = ballot(fl) != 0ull;
-    G.mext = uni_d(wave_max_d(G.mem ? fmax(fabs(dx), fmax(fabs(dy), fabs(dz))) : 0.0));
-    G.d = G.mem ? sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx))) : 0.0;
-    G.R = uni_d(wave_max_d(G.d));
-    G.H = uni_d(wave_max_d(G.h));
-    return G;
-}
-
-// filter pass: masks[ch*gm + m] for the members in `need`
-//   mode 0: r2 < mh[m] (= h_m^2, density),  mode 1: j != i_m and r2 < max(h_m, h_j)^2
-template <int MODE>
-__device__ __forceinline__ void filter_pass(const Geom &geo, const GroupLds &S, int gm, int nc,
-                                            uint64_t need, double L, bool wrap)
+// density count pass over the group superset: masks of r2 < h2, their count
+__device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, const Member &M,
+                                          double h2, bool wrap, uint64_t *masks)
 {
     const int lane = lane_id();
-    const int nch = uni((nc + 63) >> 6);
+    const int nc = M.s.nc;
+    const int nch = (nc + 63) >> 6;
+    const int32_t *cg = cand + M.s.c0;
+    int cnt = 0;
     for (int ch = 0; ch < nch; ch++) {
-        int slot = (ch << 6) + lane;
-        bool v = slot < nc;
-        int j = v ? S.cand[slot] : 0;
-        double xj = geo.x[j], yj = geo.y[j], zj = geo.z[j];
-        double hj = MODE == 1 ? geo.h[j] : 0.0;
-        uint64_t mm = 0ull;
-        uint64_t nd = need;
-        while (nd) {
-            const int m = ctz64(nd);
-            nd &= nd - 1ull;
-            double r2 = r2_of(xj, yj, zj, S.mx[m], S.my[m], S.mz[m], L, wrap);
-            bool hit;
-            if (MODE == 0) {
-                hit = r2 < S.mh[m];
-            } else {
-                double hm = fmax(S.mh[m], hj);
-                hit = (j != S.mi[m]) && (r2 < hm * hm);
-            }
-            mm = writelane_u64(mm, ballot(v && hit), m);
-        }
-        if ((need >> lane) & 1ull) S.masks[ch * gm + lane] = mm;
+        const int slot = (ch << 6) + lane;
+        const bool v = slot < nc;
+        const int j = v ? cg[slot] : 0;
+        const double r2 = r2_of(geo.x[j], geo.y[j], geo.z[j], M.xi, M.yi, M.zi, M.bx.L, wrap);
+        const uint64_t hm = ballot(v && r2 < h2);
+        if (lane == 0) masks[ch] = hm;
+        cnt += popc64(hm);
     }
     wave_lds_sync();
+    return uni(cnt);
 }
 
-// stream the neighbours of member m (masks) through a FIFO into `consume`
+// stream the neighbours recorded in `masks` through the FIFO
 template <class F>
-__device__ __forceinline__ void consume_member(const GroupLds &S, int gm, int nc, int m, F &consume)
+__device__ __forceinline__ void stream_masks(const int32_t *cand, const Member &M, const uint64_t *masks,
+                                             Fifo &q, F &consume)
 {
     const int lane = lane_id();
-    const int nch = uni((nc + 63) >> 6);
-    Fifo q{S.pend, 0};
+    const int nch = (M.s.nc + 63) >> 6;
+    const int32_t *cg = cand + M.s.c0;
     for (int ch = 0; ch < nch; ch++) {
-        uint64_t M = S.masks[ch * gm + m];
-        M = readlane_u64(M, 0);
-        int slot = (ch << 6) + lane;
-        bool hit = (M >> lane) & 1ull;
-        int j = hit ? S.cand[slot] : 0;
+        uint64_t mk = masks[ch];
+        mk = readlane_u64(mk, 0);
+        if (!mk) continue;
+        const bool hit = (mk >> lane) & 1ull;
+        const int j = hit ? cg[(ch << 6) + lane] : 0;
         q.push(hit, j, consume);
     }
     q.flush(consume);
 }
 
-// counts |{j : r2 < h2}| over walked particles
+// counts |{j : r2 < h2}| over walked particles (solo path)
 struct CountVisit {
     const double *x, *y, *z;
     double xi, yi, zi, L, h2;
@@ -561,12 +653,12 @@ template <int MODE, class F> struct StreamVisit {
 struct DensK {
     Geom g;
     GroupArg ga;
+    CandArg ca;
     const float *m;
     float *rho, *fgrad;
     sfc_density_out out;
     DevStatus *st;
     int n_ngb, dn, max_iter, fixed_h;
-    double skin;
 };
 
 namespace {
@@ -599,18 +691,18 @@ template <int KER, typename ACC> struct DensPair {
 };
 
 template <int KER, typename ACC>
-__device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, double xi, double yi, double zi,
-                                                        double h, double L, bool wrap)
+__device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, const Member &M, double h,
+                                                        bool wrap)
 {
     DensPair<KER, ACC> pp;
     pp.x = k.g.x;
     pp.y = k.g.y;
     pp.z = k.g.z;
     pp.m = k.m;
-    pp.xi = xi;
-    pp.yi = yi;
-    pp.zi = zi;
-    pp.L = L;
+    pp.xi = M.xi;
+    pp.yi = M.yi;
+    pp.zi = M.zi;
+    pp.L = M.bx.L;
     pp.wrap = wrap;
     pp.hinv = (ACC)(1.0 / h);
     return pp;
@@ -644,16 +736,15 @@ __device__ void dens_write(const DensK &k, int i, double h, int nn, int it, bool
 
 // one particle on its own: one walk per h evaluation, then the sums
 template <int KER, typename ACC>
-__device__ void dens_solo(const DensK &k, const GroupLds &S, int i, double h, double lo, double hi,
-                          int it, double L, int root, int root_end)
+__device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, double h, double lo,
+                          double hi, int it)
 {
-    const double xi = uni_d(k.g.x[i]), yi = uni_d(k.g.y[i]), zi = uni_d(k.g.z[i]);
     int nn = 0;
     bool conv = false;
     for (int guard = 0; guard <= k.max_iter; guard++) {
-        Ball B{xi, yi, zi, L, sq(h * INFL), 0.0, 0.0, 0};
-        CountVisit cv{k.g.x, k.g.y, k.g.z, xi, yi, zi, L, h * h, 0};
-        walk(k.g, root, root_end, B, S.wl, cv, k.st);
+        Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
+        CountVisit cv{k.g.x, k.g.y, k.g.z, M.xi, M.yi, M.zi, M.bx.L, h * h, 0};
+        walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, cv, k.st);
         if (lane_id() == 0) atomicAdd(&k.st->n_walks, 1ull);
         nn = uni(cv.cnt);
         it++;
@@ -666,95 +757,59 @@ __device__ void dens_solo(const DensK &k, const GroupLds &S, int i, double h, do
         lo = uni_d(lo);
         hi = uni_d(hi);
     }
-    DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, xi, yi, zi, h, L, true);
-    StreamVisit<0, DensPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, xi, yi, zi, L, h, i,
-                                          Fifo{S.pend, 0}, &pp};
-    Ball B{xi, yi, zi, L, sq(h * INFL), 0.0, 0.0, 0};
-    walk(k.g, root, root_end, B, S.wl, sv, k.st);
+    DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, true);
+    StreamVisit<0, DensPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi, M.bx.L, h, M.i,
+                                          Fifo{S.fifo, 0}, &pp};
+    Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
+    walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, sv, k.st);
     sv.q.flush(pp);
-    dens_write<KER, ACC>(k, i, h, nn, it, conv, pp);
+    dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp);
 }
 
 } // namespace
 
-template <int KER, typename ACC> __global__ __launch_bounds__(64) void k_density(DensK k)
+// One wave per active particle: h iteration on the group superset, then the
+// density sums.
+template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_density(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const GroupLds S = carve(lds_raw, k.ga.T, k.ga.gm);
-    const int lane = lane_id();
-    const int G = uni(*k.ga.n_groups);
-    const GroupRange gr = group_range(G);
-    for (int g = gr.g; g < gr.end; g += gr.stride) {
-        const GroupHead H = group_head(k.g, k.ga, g);
-        const double cov = H.R + k.skin * H.H;
-        Ball B{H.cx, H.cy, H.cz, H.L, sq(cov * INFL), 0.0, 0.0, 0};
-        AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, S.cand, k.ga.T, 0, false, false, B, 0.0};
-        walk(k.g, H.root, H.root_end, B, S.wl, ap, k.st);
-        if (lane == 0) {
-            atomicAdd(&k.st->n_walks, 1ull);
-            atomicAdd(&k.st->sum_cand, (unsigned long long)ap.n);
-        }
-        double h = H.h, lo = 0.0, hi = INFINITY;
+    const MemLds S = mem_carve(lds_raw, k.ga.T);
+    const int A = uni(*k.ga.n_act);
+    const ItemRange ar = item_range(A);
+    for (int a = ar.i; a < ar.end; a += ar.stride) {
+        const Member M = member(k.g, k.ga, k.ca, a);
+        double h = M.h, lo = 0.0, hi = INFINITY;
         int it = 0, nn = 0;
-        bool done = !H.mem, conv = false, solo = false;
-        if (uni_b(ap.over)) {
-            solo = H.mem;
-            if (lane == 0) atomicAdd(&k.st->n_overflow, 1ull);
-        } else {
-            const int nc = uni(ap.n);
-            const bool wrap = pair_wrap(uni_b(ap.folded), ap.ext, H.mfold, H.mext, H.L);
-            const int nch = (nc + 63) >> 6;
+        bool conv = false, solo = (M.s.flags & GSUP_SOLO) != 0;
+        const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
+        if (!solo) {
             for (int pass = 0; pass <= k.max_iter; pass++) {
-                if (!done && !solo && !(h + H.d <= cov)) solo = true;
-                const uint64_t need = ballot(!done && !solo);
-                if (!need) break;
-                if ((need >> lane) & 1ull) {
-                    S.mx[lane] = H.xi;
-                    S.my[lane] = H.yi;
-                    S.mz[lane] = H.zi;
-                    S.mh[lane] = h * h;
+                if (!(h + M.d <= M.s.cov)) {
+                    solo = true;
+                    break;
                 }
-                wave_lds_sync();
-                filter_pass<0>(k.g, S, k.ga.gm, nc, need, H.L, wrap);
-                if ((need >> lane) & 1ull) {
-                    int cnt = 0;
-                    for (int ch = 0; ch < nch; ch++) cnt += popc64(S.masks[ch * k.ga.gm + lane]);
-                    nn = cnt;
-                    it++;
-                    if (k.fixed_h || (cnt >= k.n_ngb - k.dn && cnt <= k.n_ngb + k.dn)) {
-                        done = true;
-                        conv = true;
-                    } else if (it >= k.max_iter) {
-                        done = true;
-                    } else {
-                        h = h_step(cnt, k.n_ngb, k.dn, h, lo, hi);
-                    }
+                nn = count_pass(k.g, k.ca.cand, M, h * h, wrap, S.masks);
+                it++;
+                if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
+                    conv = true;
+                    break;
                 }
+                if (it >= k.max_iter) break;
+                h = uni_d(h_step(nn, k.n_ngb, k.dn, h, lo, hi));
+                lo = uni_d(lo);
+                hi = uni_d(hi);
                 if (pass == k.max_iter) guard_hit(k.st);
             }
-            uint64_t fin = ballot(done && H.mem);
-            while (fin) {
-                const int m = ctz64(fin);
-                fin &= fin - 1ull;
-                const double hm = uni_d(readlane_d(h, m));
-                DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, uni_d(readlane_d(H.xi, m)),
-                                                            uni_d(readlane_d(H.yi, m)),
-                                                            uni_d(readlane_d(H.zi, m)), hm, H.L, wrap);
-                consume_member(S, k.ga.gm, nc, m, pp);
-                dens_write<KER, ACC>(k, uni(readlane_i(H.i, m)), hm, uni(readlane_i(nn, m)),
-                                     uni(readlane_i(it, m)), ballot(conv && lane == m) != 0ull, pp);
-            }
         }
-        // members that left the superset finish alone, in this wave
-        uint64_t rest = ballot(solo);
-        if (rest && lane == 0) atomicAdd(&k.st->n_deferred, (unsigned long long)popc64(rest));
-        while (rest) {
-            const int m = ctz64(rest);
-            rest &= rest - 1ull;
-            dens_solo<KER, ACC>(k, S, uni(readlane_i(H.i, m)), uni_d(readlane_d(h, m)),
-                                uni_d(readlane_d(lo, m)), uni_d(readlane_d(hi, m)),
-                                uni(readlane_i(it, m)), H.L, H.root, H.root_end);
+        if (solo) {
+            if (lane_id() == 0) atomicAdd(&k.st->n_deferred, 1ull);
+            dens_solo<KER, ACC>(k, S, M, h, lo, hi, it);
+            continue;
         }
+        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, wrap);
+        Fifo q{S.fifo, 0};
+        stream_masks(k.ca.cand, M, S.masks, q, pp);
+        dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp);
     }
 }
 
@@ -762,7 +817,10 @@ template <int KER, typename ACC> __global__ __launch_bounds__(64) void k_density
 struct HydroK {
     Geom g;
     GroupArg ga;
-    const float *m, *vx, *vy, *vz, *u, *rho, *fgrad, *pf, *cs;
+    CandArg ca;
+    const float *m, *vx, *vy, *vz, *u, *rho, *fgrad;
+    const float4 *pa; // per particle: m, vx, vy, vz
+    const float4 *pb; // per particle: rho, f P / rho^2, sound speed, h
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
@@ -787,34 +845,46 @@ template <int KER, typename ACC> struct HydroPair {
             dzd = fold(dzd, L);
         }
         ACC dx = (ACC)dxd, dy = (ACC)dyd, dz = (ACC)dzd;
+        ACC mj, vxj, vyj, vzj, rhoj, pfj, csj, hj;
+        if (sizeof(ACC) == 8) {
+            double gm1 = k->gamma - 1.0;
+            double uj = k->u[j];
+            rhoj = (ACC)k->rho[j];
+            pfj = (ACC)(k->fgrad[j] * gm1 * uj / (double)k->rho[j]);
+            csj = (ACC)sqrt(k->gamma * gm1 * uj);
+            hj = (ACC)k->g.h[j];
+            mj = (ACC)k->m[j];
+            vxj = (ACC)k->vx[j];
+            vyj = (ACC)k->vy[j];
+            vzj = (ACC)k->vz[j];
+        } else {
+            const float4 a = k->pa[j];
+            const float4 b = k->pb[j];
+            mj = (ACC)a.x;
+            vxj = (ACC)a.y;
+            vyj = (ACC)a.z;
+            vzj = (ACC)a.w;
+            rhoj = (ACC)b.x;
+            pfj = (ACC)b.y;
+            csj = (ACC)b.z;
+            hj = (ACC)b.w;
+        }
         ACC r2 = mad(dz, dz, mad(dy, dy, dx * dx));
         ACC r = sqrt(r2);
         ACC rinv = r > ACC(0) ? ACC(1) / r : ACC(0);
         ACC w, dwi, dwj;
         kern_eval<KER, ACC>(r * hinv, w, dwi);
-        ACC hjinv = ACC(1) / (ACC)k->g.h[j];
+        ACC hjinv = ACC(1) / hj;
         kern_eval<KER, ACC>(r * hjinv, w, dwj);
         ACC hj2 = hjinv * hjinv;
         ACC dWi = C * dwi * hinv4;
         ACC dWj = C * dwj * (hj2 * hj2);
         ACC dWb = ACC(0.5) * (dWi + dWj);
-        ACC rhoj = (ACC)k->rho[j];
-        ACC pfj, csj;
-        if (sizeof(ACC) == 8) {
-            double gm1 = k->gamma - 1.0;
-            double uj = k->u[j];
-            pfj = (ACC)(k->fgrad[j] * gm1 * uj / (double)k->rho[j]);
-            csj = (ACC)sqrt(k->gamma * gm1 * uj);
-        } else {
-            pfj = (ACC)k->pf[j];
-            csj = (ACC)k->cs[j];
-        }
-        ACC vdx = vx - (ACC)k->vx[j], vdy = vy - (ACC)k->vy[j], vdz = vz - (ACC)k->vz[j];
+        ACC vdx = vx - vxj, vdy = vy - vyj, vdz = vz - vzj;
         ACC vr = mad(vdz, dz, mad(vdy, dy, vdx * dx));
         ACC wij = vr < ACC(0) ? vr * rinv : ACC(0);
         ACC vsig = cs + csj - ACC(3) * wij;
         ACC visc = -(ACC)k->alpha * vsig * wij / (rho + rhoj);
-        ACC mj = (ACC)k->m[j];
         ACC fac = mj * (pf * dWi + pfj * dWj + visc * dWb);
         ACC fr = fac * rinv;
         ax.add(-fr * dx);
@@ -826,17 +896,17 @@ template <int KER, typename ACC> struct HydroPair {
 };
 
 template <int KER, typename ACC>
-__device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, int i, double xi, double yi,
-                                                          double zi, double h, double L, bool wrap)
+__device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, const Member &M, bool wrap)
 {
+    const int i = M.i;
     HydroPair<KER, ACC> hp;
     hp.k = &k;
-    hp.xi = xi;
-    hp.yi = yi;
-    hp.zi = zi;
-    hp.L = L;
+    hp.xi = M.xi;
+    hp.yi = M.yi;
+    hp.zi = M.zi;
+    hp.L = M.bx.L;
     hp.wrap = wrap;
-    double hinv = 1.0 / h;
+    double hinv = 1.0 / M.h;
     hp.hinv = (ACC)hinv;
     hp.hinv4 = (ACC)(hinv * hinv * hinv * hinv);
     hp.vx = (ACC)k.vx[i];
@@ -875,87 +945,62 @@ __device__ void hydro_write(const HydroK &k, int i, const HydroPair<KER, ACC> &h
     if (k.out.az64) k.out.az64[i] = az;
     if (k.out.dudt64) k.out.dudt64[i] = du;
 }
-
-template <int KER, typename ACC>
-__device__ void hydro_solo(const HydroK &k, const GroupLds &S, int i, double L, int root, int root_end)
-{
-    const double xi = uni_d(k.g.x[i]), yi = uni_d(k.g.y[i]), zi = uni_d(k.g.z[i]);
-    const double h = uni_d(k.g.h[i]);
-    HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, i, xi, yi, zi, h, L, true);
-    StreamVisit<1, HydroPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, xi, yi, zi, L, h, i,
-                                           Fifo{S.pend, 0}, &hp};
-    Ball B{xi, yi, zi, L, 0.0, 0.0, h, 1};
-    walk(k.g, root, root_end, B, S.wl, sv, k.st);
-    if (lane_id() == 0) atomicAdd(&k.st->n_walks, 1ull);
-    sv.q.flush(hp);
-    hydro_write<KER, ACC>(k, i, hp);
-}
 } // namespace
 
-__global__ void k_hydro_prep(int64_t n, const float *__restrict__ rho,
-                             const float *__restrict__ fgrad, const float *__restrict__ u,
-                             double gamma, float *__restrict__ pf, float *__restrict__ cs)
+__global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float *__restrict__ vx,
+                             const float *__restrict__ vy, const float *__restrict__ vz,
+                             const float *__restrict__ rho, const float *__restrict__ fgrad,
+                             const float *__restrict__ u, const double *__restrict__ h,
+                             double gamma, float4 *__restrict__ pa, float4 *__restrict__ pb)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double gm1 = gamma - 1.0;
     double uu = u[i];
-    pf[i] = (float)(fgrad[i] * gm1 * uu / (double)rho[i]);
-    cs[i] = (float)sqrt(gamma * gm1 * uu);
+    pa[i] = make_float4(m[i], vx[i], vy[i], vz[i]);
+    pb[i] = make_float4(rho[i], (float)(fgrad[i] * gm1 * uu / (double)rho[i]),
+                        (float)sqrt(gamma * gm1 * uu), (float)h[i]);
 }
 
-template <int KER, typename ACC> __global__ __launch_bounds__(64) void k_hydro(HydroK k)
+// One wave per active particle: filter the group superset with
+// r < max(h_i, h_j), j != i, and sum the forces.
+template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const GroupLds S = carve(lds_raw, k.ga.T, k.ga.gm);
+    const MemLds S = mem_carve(lds_raw, k.ga.T);
     const int lane = lane_id();
-    const int G = uni(*k.ga.n_groups);
-    const GroupRange gr = group_range(G);
-    for (int g = gr.g; g < gr.end; g += gr.stride) {
-        const GroupHead H = group_head(k.g, k.ga, g);
-        Ball B{H.cx, H.cy, H.cz, H.L, 0.0, H.R, H.H, 1};
-        AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, S.cand, k.ga.T, 0, false, false, B, 0.0};
-        walk(k.g, H.root, H.root_end, B, S.wl, ap, k.st);
-        if (lane == 0) {
-            atomicAdd(&k.st->n_walks, 1ull);
-            atomicAdd(&k.st->sum_cand, (unsigned long long)ap.n);
-        }
-        const uint64_t need = ballot(H.mem);
-        if (uni_b(ap.over)) {
-            if (lane == 0) {
-                atomicAdd(&k.st->n_overflow, 1ull);
-                atomicAdd(&k.st->n_deferred, (unsigned long long)popc64(need));
-            }
-            uint64_t rest = need;
-            while (rest) {
-                const int m = ctz64(rest);
-                rest &= rest - 1ull;
-                hydro_solo<KER, ACC>(k, S, uni(readlane_i(H.i, m)), H.L, H.root, H.root_end);
-            }
+    const int A = uni(*k.ga.n_act);
+    const ItemRange ar = item_range(A);
+    for (int a = ar.i; a < ar.end; a += ar.stride) {
+        const Member M = member(k.g, k.ga, k.ca, a);
+        if (M.s.flags & GSUP_SOLO) {
+            if (lane == 0) atomicAdd(&k.st->n_deferred, 1ull);
+            HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
+            StreamVisit<1, HydroPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
+                                                   M.bx.L, M.h, M.i, Fifo{S.fifo, 0}, &hp};
+            Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
+            walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, sv, k.st);
+            if (lane == 0) atomicAdd(&k.st->n_walks, 1ull);
+            sv.q.flush(hp);
+            hydro_write<KER, ACC>(k, M.i, hp);
             continue;
         }
-        const int nc = uni(ap.n);
-        const bool wrap = pair_wrap(uni_b(ap.folded), ap.ext, H.mfold, H.mext, H.L);
-        if (H.mem) {
-            S.mx[lane] = H.xi;
-            S.my[lane] = H.yi;
-            S.mz[lane] = H.zi;
-            S.mh[lane] = H.h;
-            S.mi[lane] = H.i;
+        const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
+        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, wrap);
+        Fifo q{S.fifo, 0};
+        const int nc = M.s.nc;
+        const int nch = (nc + 63) >> 6;
+        const int32_t *cg = k.ca.cand + M.s.c0;
+        for (int ch = 0; ch < nch; ch++) {
+            const int slot = (ch << 6) + lane;
+            const bool v = slot < nc;
+            const int j = v ? cg[slot] : 0;
+            const double r2 = r2_of(k.g.x[j], k.g.y[j], k.g.z[j], M.xi, M.yi, M.zi, M.bx.L, wrap);
+            const double hm = fmax(M.h, k.g.h[j]);
+            q.push(v && j != M.i && r2 < hm * hm, j, hp);
         }
-        wave_lds_sync();
-        filter_pass<1>(k.g, S, k.ga.gm, nc, need, H.L, wrap);
-        uint64_t fin = need;
-        while (fin) {
-            const int m = ctz64(fin);
-            fin &= fin - 1ull;
-            const int im = uni(readlane_i(H.i, m));
-            HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(
-                k, im, uni_d(readlane_d(H.xi, m)), uni_d(readlane_d(H.yi, m)),
-                uni_d(readlane_d(H.zi, m)), uni_d(readlane_d(H.h, m)), H.L, wrap);
-            consume_member(S, k.ga.gm, nc, m, hp);
-            hydro_write<KER, ACC>(k, im, hp);
-        }
+        q.flush(hp);
+        hydro_write<KER, ACC>(k, M.i, hp);
     }
 }
 
@@ -963,6 +1008,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(64) void k_hydro(H
 struct VerK {
     Geom g;
     GroupArg ga;
+    CandArg ca;
     sfc_verify ver;
     const uint32_t *orig;
     DevStatus *st;
@@ -1035,76 +1081,48 @@ struct VerVisit {
         (*va)(j, hit);
     }
 };
-
-__device__ void verify_solo(const VerK &k, const GroupLds &S, int i, double L, int root, int root_end)
-{
-    const double xi = uni_d(k.g.x[i]), yi = uni_d(k.g.y[i]), zi = uni_d(k.g.z[i]);
-    const double h = uni_d(k.g.h[i]);
-    VerifyAcc va = verify_init(k, i);
-    VerVisit vv{k.g.x, k.g.y, k.g.z, k.g.h, xi, yi, zi, L, h, i, k.ver.mode, &va};
-    Ball B = k.ver.mode == 0 ? Ball{xi, yi, zi, L, sq(h * INFL), 0.0, 0.0, 0}
-                             : Ball{xi, yi, zi, L, 0.0, 0.0, h, 1};
-    walk(k.g, root, root_end, B, S.wl, vv, k.st);
-    verify_write(k, i, va);
-}
 } // namespace
 
-__global__ __launch_bounds__(64) void k_verify(VerK k)
+// One wave per active particle: its neighbour set from the group superset
+// (count, fingerprint, optional list in ascending order).
+__global__ __launch_bounds__(256) void k_verify(VerK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const GroupLds S = carve(lds_raw, k.ga.T, k.ga.gm);
+    const MemLds S = mem_carve(lds_raw, k.ga.T);
     const int lane = lane_id();
-    const int G = uni(*k.ga.n_groups);
     const int mode = k.ver.mode;
-    const GroupRange gr = group_range(G);
-    for (int g = gr.g; g < gr.end; g += gr.stride) {
-        const GroupHead H = group_head(k.g, k.ga, g);
-        const double cov = H.R + H.H;
-        Ball B = mode == 0 ? Ball{H.cx, H.cy, H.cz, H.L, sq(cov * INFL), 0.0, 0.0, 0}
-                           : Ball{H.cx, H.cy, H.cz, H.L, 0.0, H.R, H.H, 1};
-        AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, S.cand, k.ga.T, 0, false, false, B, 0.0};
-        walk(k.g, H.root, H.root_end, B, S.wl, ap, k.st);
-        if (lane == 0) {
-            atomicAdd(&k.st->n_walks, 1ull);
-            atomicAdd(&k.st->sum_cand, (unsigned long long)ap.n);
-        }
-        const uint64_t need = ballot(H.mem);
-        if (uni_b(ap.over)) {
-            if (lane == 0) atomicAdd(&k.st->n_overflow, 1ull);
-            uint64_t rest = need;
-            while (rest) {
-                const int m = ctz64(rest);
-                rest &= rest - 1ull;
-                verify_solo(k, S, uni(readlane_i(H.i, m)), H.L, H.root, H.root_end);
-            }
+    const int A = uni(*k.ga.n_act);
+    const ItemRange ar = item_range(A);
+    for (int a = ar.i; a < ar.end; a += ar.stride) {
+        const Member M = member(k.g, k.ga, k.ca, a);
+        VerifyAcc va = verify_init(k, M.i);
+        if (M.s.flags & GSUP_SOLO) {
+            VerVisit vv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi, M.bx.L, M.h, M.i, mode, &va};
+            Ball B = mode == 0 ? Ball{M.xi, M.yi, M.zi, M.bx.L, sq(M.h * INFL), 0.0, 0.0, 0}
+                               : Ball{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
+            walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, vv, k.st);
+            verify_write(k, M.i, va);
             continue;
         }
-        const int nc = uni(ap.n);
-        const bool wrap = pair_wrap(uni_b(ap.folded), ap.ext, H.mfold, H.mext, H.L);
-        if (H.mem) {
-            S.mx[lane] = H.xi;
-            S.my[lane] = H.yi;
-            S.mz[lane] = H.zi;
-            S.mh[lane] = mode == 0 ? H.h * H.h : H.h;
-            S.mi[lane] = H.i;
-        }
-        wave_lds_sync();
-        if (mode == 0) filter_pass<0>(k.g, S, k.ga.gm, nc, need, H.L, wrap);
-        else filter_pass<1>(k.g, S, k.ga.gm, nc, need, H.L, wrap);
-        uint64_t fin = need;
+        const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
+        const int nc = M.s.nc;
         const int nch = (nc + 63) >> 6;
-        while (fin) {
-            const int m = ctz64(fin);
-            fin &= fin - 1ull;
-            const int im = uni(readlane_i(H.i, m));
-            VerifyAcc va = verify_init(k, im);
-            for (int ch = 0; ch < nch; ch++) {
-                uint64_t M = readlane_u64(S.masks[ch * k.ga.gm + m], 0);
-                bool hit = (M >> lane) & 1ull;
-                va(hit ? S.cand[(ch << 6) + lane] : 0, hit);
+        const int32_t *cg = k.ca.cand + M.s.c0;
+        for (int ch = 0; ch < nch; ch++) {
+            const int slot = (ch << 6) + lane;
+            const bool v = slot < nc;
+            const int j = v ? cg[slot] : 0;
+            const double r2 = r2_of(k.g.x[j], k.g.y[j], k.g.z[j], M.xi, M.yi, M.zi, M.bx.L, wrap);
+            bool hit;
+            if (mode == 0) {
+                hit = r2 < M.h * M.h;
+            } else {
+                const double hm = fmax(M.h, k.g.h[j]);
+                hit = j != M.i && r2 < hm * hm;
             }
-            verify_write(k, im, va);
+            va(j, v && hit);
         }
+        verify_write(k, M.i, va);
     }
 }
 
@@ -1127,54 +1145,89 @@ Geom make_geom(const PartDev &p, const TreeDev &t)
     return g;
 }
 
-GroupArg make_groups(const GroupBufs &gb, int T, int gm)
+GroupArg make_groups(const GroupBufs &gb, int T)
 {
     GroupArg a;
     a.act = gb.act;
     a.goff = gb.goff;
     a.n_groups = gb.n_groups;
+    a.n_act = gb.n_act;
     a.T = T;
-    a.gm = gm;
     return a;
 }
 
-// waves: as many as fit on the chip at once (a multiple of 8, one per
-// workgroup), so that every wave is resident and keeps its XCD's groups
+CandArg make_cand(const SearchBufs &sb)
+{
+    CandArg c;
+    c.cand = sb.cand;
+    c.cap = sb.cand_cap;
+    c.sup = sb.sup;
+    c.grp = sb.grp;
+    return c;
+}
+
+// persistent grid: as many workgroups as fit on the chip at once (a multiple
+// of 8), so that every wave is resident and keeps its XCD's items
 template <class Kern>
-int64_t wave_count(Kern kern, size_t lds, int cu, int64_t max_groups)
+unsigned grid_size(Kern kern, int threads, size_t lds, int cu, int64_t max_items)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess ||
         per_cu < 1)
-        per_cu = 8;
+        per_cu = 2;
     int64_t w = (int64_t)cu * per_cu;
-    int64_t cap = ((max_groups + 7) / 8) * 8;
+    const int64_t need = (max_items + threads / 64 - 1) / (threads / 64);
+    const int64_t cap = ((need + 7) / 8) * 8;
     if (cap < w) w = cap;
     w = (w / 8) * 8;
-    return w < 8 ? 8 : w;
+    return (unsigned)(w < 8 ? 8 : w);
 }
 
 template <class Kern, class Arg>
-hipError_t launch_waves(Kern kern, hipStream_t s, const Arg &a, size_t lds, int cu, int64_t max_groups)
+hipError_t launch_persistent(Kern kern, hipStream_t s, const Arg &a, int threads, size_t lds, int cu,
+                             int64_t max_items)
 {
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    kern<<<(unsigned)wave_count(kern, lds, cu, max_groups), 64, lds, s>>>(a);
+    kern<<<grid_size(kern, threads, lds, cu, max_items), threads, lds, s>>>(a);
     return hipGetLastError();
+}
+
+constexpr int MEM_WAVES = 4; // member waves per workgroup
+
+hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                       SearchBufs &sb, DevStatus *st, int T, double skin, int hydro)
+{
+    k_reset_top<<<1, 64, 0, s>>>(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    WalkK k;
+    memset(&k, 0, sizeof(k));
+    k.g = make_geom(p, t);
+    k.ga = make_groups(g, T);
+    k.ca = make_cand(sb);
+    k.st = st;
+    k.skin = skin;
+    k.hydro = hydro;
+    const size_t lds = (size_t)4 * T + 4 * (64 + 66 + 2);
+    return launch_persistent(k_walk, s, k, 64, lds, sb.cu_count, p.n);
 }
 } // namespace
 
 hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                          SearchBufs &sb, const DensityArgs &a, DevStatus *st, int gm)
+                          SearchBufs &sb, const DensityArgs &a, DevStatus *st)
 {
     const sfc_density_params &dp = a.dp;
+    hipError_t e = launch_walk(s, p, t, g, sb, st, dp.t_cand, dp.skin, 0);
+    if (e != hipSuccess) return e;
     DensK k;
     memset(&k, 0, sizeof(k));
     k.g = make_geom(p, t);
-    k.ga = make_groups(g, dp.t_cand, gm);
+    k.ga = make_groups(g, dp.t_cand);
+    k.ca = make_cand(sb);
     k.m = p.m;
     k.rho = p.rho;
     k.fgrad = p.fgrad;
@@ -1184,28 +1237,33 @@ hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, con
     k.dn = dp.dn;
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
-    k.skin = dp.skin;
-    const size_t lds = group_lds_bytes(dp.t_cand, gm);
+    const size_t lds = MEM_WAVES * mem_lds_bytes(dp.t_cand);
+    const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;
     if (dp.kernel == 0 && dp.accum == SFC_ACCUM_F32)
-        return launch_waves(k_density<0, float>, s, k, lds, sb.cu_count, n);
-    if (dp.kernel == 0) return launch_waves(k_density<0, double>, s, k, lds, sb.cu_count, n);
-    if (dp.accum == SFC_ACCUM_F32) return launch_waves(k_density<1, float>, s, k, lds, sb.cu_count, n);
-    return launch_waves(k_density<1, double>, s, k, lds, sb.cu_count, n);
+        return launch_persistent(k_density<0, float>, s, k, th, lds, sb.cu_count, n);
+    if (dp.kernel == 0) return launch_persistent(k_density<0, double>, s, k, th, lds, sb.cu_count, n);
+    if (dp.accum == SFC_ACCUM_F32)
+        return launch_persistent(k_density<1, float>, s, k, th, lds, sb.cu_count, n);
+    return launch_persistent(k_density<1, double>, s, k, th, lds, sb.cu_count, n);
 }
 
 hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                        SearchBufs &sb, const HydroArgs &a, DevStatus *st, int gm)
+                        SearchBufs &sb, const HydroArgs &a, DevStatus *st)
 {
     const sfc_hydro_params &hp = a.hp;
-    k_hydro_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.rho, p.fgrad, p.u, hp.gamma,
-                                                               sb.pf, sb.cs);
+    k_hydro_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.m, p.vx, p.vy, p.vz, p.rho,
+                                                               p.fgrad, p.u, p.h, hp.gamma, sb.pa,
+                                                               sb.pb);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_walk(s, p, t, g, sb, st, hp.t_cand, 1.0, 1);
     if (e != hipSuccess) return e;
     HydroK k;
     memset(&k, 0, sizeof(k));
     k.g = make_geom(p, t);
-    k.ga = make_groups(g, hp.t_cand, gm);
+    k.ga = make_groups(g, hp.t_cand);
+    k.ca = make_cand(sb);
     k.m = p.m;
     k.vx = p.vx;
     k.vy = p.vy;
@@ -1213,30 +1271,36 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.u = p.u;
     k.rho = p.rho;
     k.fgrad = p.fgrad;
-    k.pf = sb.pf;
-    k.cs = sb.cs;
+    k.pa = sb.pa;
+    k.pb = sb.pb;
     k.out = a.out;
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
-    const size_t lds = group_lds_bytes(hp.t_cand, gm);
+    const size_t lds = MEM_WAVES * mem_lds_bytes(hp.t_cand);
+    const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;
     if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32)
-        return launch_waves(k_hydro<0, float>, s, k, lds, sb.cu_count, n);
-    if (hp.kernel == 0) return launch_waves(k_hydro<0, double>, s, k, lds, sb.cu_count, n);
-    if (hp.accum == SFC_ACCUM_F32) return launch_waves(k_hydro<1, float>, s, k, lds, sb.cu_count, n);
-    return launch_waves(k_hydro<1, double>, s, k, lds, sb.cu_count, n);
+        return launch_persistent(k_hydro<0, float>, s, k, th, lds, sb.cu_count, n);
+    if (hp.kernel == 0) return launch_persistent(k_hydro<0, double>, s, k, th, lds, sb.cu_count, n);
+    if (hp.accum == SFC_ACCUM_F32)
+        return launch_persistent(k_hydro<1, float>, s, k, th, lds, sb.cu_count, n);
+    return launch_persistent(k_hydro<1, double>, s, k, th, lds, sb.cu_count, n);
 }
 
 hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st, int gm)
+                         SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st)
 {
+    hipError_t e = launch_walk(s, p, t, g, sb, st, t_cand, 1.0, v.mode == 1 ? 1 : 0);
+    if (e != hipSuccess) return e;
     VerK k;
     memset(&k, 0, sizeof(k));
     k.g = make_geom(p, t);
-    k.ga = make_groups(g, t_cand, gm);
+    k.ga = make_groups(g, t_cand);
+    k.ca = make_cand(sb);
     k.ver = v;
     k.orig = p.orig;
     k.st = st;
-    return launch_waves(k_verify, s, k, group_lds_bytes(t_cand, gm), sb.cu_count, p.n);
+    return launch_persistent(k_verify, s, k, 64 * MEM_WAVES, MEM_WAVES * mem_lds_bytes(t_cand),
+                             sb.cu_count, p.n);
 }

@@ -41,7 +41,7 @@ class SfcError(RuntimeError):
 
 class Dims(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_boxes", C.c_int32), ("n_leaf_min", C.c_int32),
-                ("t_cand_max", C.c_int32)]
+                ("t_cand_max", C.c_int32), ("cand_per_particle", C.c_int32)]
 
 
 class CParticles(C.Structure):
@@ -224,7 +224,7 @@ class Context:
     """A library context bound to a torch stream and a device workspace."""
 
     def __init__(self, n: int, n_boxes: int = 1, n_leaf_min: int = 8, t_cand_max: int = 4096,
-                 stream=None):
+                 stream=None, cand_per_particle: int = 0):
         import torch
         self.L = load_library()
         if not torch.cuda.is_available():
@@ -233,7 +233,7 @@ class Context:
         h = _P()
         self._check(self.L.sfc_ctx_create(C.byref(h), _P(self.stream.cuda_stream)), None)
         self.h = h
-        self.dims = Dims(n, n_boxes, n_leaf_min, t_cand_max)
+        self.dims = Dims(n, n_boxes, n_leaf_min, t_cand_max, cand_per_particle)
         nbytes = self.L.sfc_workspace_bytes(C.byref(self.dims))
         if nbytes == 0:
             raise SfcError(SFC_EINVAL, f"invalid workspace dims {n}, {n_boxes}")
