@@ -122,7 +122,8 @@ struct DevStatus {
     unsigned long long sum_cand;
     unsigned long long n_walks;
     unsigned long long sum_iters;
-    unsigned long long cand_top; // bump pointer of the candidate buffer (per walk launch)
+    unsigned long long cand_top; // bump pointer of the candidate buffer (per pass)
+    int32_t qctr[16];            // per-XCD work counters of the walk kernel (per pass)
     int32_t pad[6];
 };
 

@@ -144,12 +144,46 @@ namespace {
 
 // ------------------------------------------------------------------ scheduling
 // Workgroups are dealt to the 8 XCDs round-robin (block b on XCD b mod 8),
-// and each XCD has its own L2.  Give each XCD one contiguous eighth of the
-// work items (groups or actives, both in Hilbert order, so an eighth is a
-// compact region of space): the waves on one XCD then share the tree nodes
-// and particles they read.  Within an XCD the waves take the items in a
-// round-robin stride, so the items in flight are neighbours, and the waves of
-// one workgroup (one CU) take consecutive items.
+// and each XCD has its own L2.  The work items (groups, or active particles,
+// both in Hilbert order) are cut into 8 contiguous ranges, one per XCD, each
+// a compact region of space, so the waves of one XCD share the tree nodes
+// and particles they read.  A wave takes the next item of its XCD's range
+// from a counter; when that range is used up it takes items from the other
+// ranges, so no XCD idles while another has work.  Every take advances a
+// counter, and a wave leaves after all 8 ranges are used up: the loop ends.
+struct Queue {
+    int32_t *ctr; // [8]
+    int n, per, xcd, xs;
+};
+__device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items)
+{
+    Queue q;
+    q.ctr = ctr;
+    q.n = n_items;
+    q.per = (n_items + 7) >> 3;
+    q.xcd = blockIdx.x & 7;
+    q.xs = 0;
+    return q;
+}
+// next item, or -1 when every range is used up
+__device__ __forceinline__ int queue_next(Queue &q)
+{
+    while (q.xs < 8) {
+        const int x = (q.xcd + q.xs) & 7;
+        int t = 0;
+        if (lane_id() == 0) t = atomicAdd(&q.ctr[x], 1);
+        t = uni(t);
+        const int item = x * q.per + t;
+        if (t < q.per && item < q.n) return item;
+        q.xs++;
+    }
+    return -1;
+}
+
+// The particle kernels keep a static split instead: the waves of one
+// workgroup (one CU) take consecutive particles, which mostly belong to the
+// same group and read the same candidates at the same time, so the CU's L1
+// serves them.
 struct ItemRange {
     int i, end, stride;
 };
@@ -393,9 +427,14 @@ struct WalkK {
     int hydro;   // 1: hydro ball R_g + max(max member h, h_j)
 };
 
-__global__ void k_reset_top(DevStatus *st)
+// per-pass reset of the candidate buffer and the work counters (a kernel,
+// not a memset, so that the step can be captured in a graph)
+__global__ void k_reset_pass(DevStatus *st)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->cand_top = 0ull;
+    const int t = threadIdx.x;
+    if (blockIdx.x != 0) return;
+    if (t == 0) st->cand_top = 0ull;
+    if (t < 16) st->qctr[t] = 0;
 }
 
 // One wave per group: the walk, the superset into the global buffer, the
@@ -408,8 +447,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     WalkLds wl{cand + T, cand + T + 64};
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
-    const ItemRange gr = item_range(G);
-    for (int g = gr.i; g < gr.end; g += gr.stride) {
+    Queue wq = queue_open(k.st->qctr, G);
+    for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
         const int a = uni(k.ga.goff[g]);
         const int nm = min(uni(k.ga.goff[g + 1]) - a, 64);
         const bool mem = lane < nm;
@@ -479,26 +518,37 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
 namespace {
 
 // ------------------------------------------------------------------ per-member set-up
+constexpr int FIFO_B = 4; // neighbour batches of 64 consumed together
+
 // LDS of one member wave: neighbour masks of the last filter pass, the FIFO
 // and the walk scratch of the solo path
+// squared distances kept (as FP32) for the first R2C_MAX candidates
+constexpr int R2C_MAX = 1024;
+__host__ __device__ constexpr int r2c_len(int T, bool cache) { return cache ? (T < R2C_MAX ? T : R2C_MAX) : 0; }
+
 struct MemLds {
     uint64_t *masks; // [T/64]
-    int *fifo;       // [128]
+    int *fifo;       // [64 * (FIFO_B + 1)]
     WalkLds wl;      // [64] + [66]
+    float *r2c;      // [r2c_len]: squared distances of the first pass
+    int rc;
 };
-__host__ __device__ constexpr size_t mem_lds_bytes(int T)
+__host__ __device__ constexpr size_t mem_lds_bytes(int T, bool cache)
 {
-    return (size_t)8 * (T / 64) + (size_t)4 * (128 + 64 + 66 + 2);
+    return (size_t)8 * (T / 64) + (size_t)4 * (64 * (FIFO_B + 1) + 64 + 66 + 2) +
+           (size_t)4 * r2c_len(T, cache);
 }
-__device__ __forceinline__ MemLds mem_carve(char *base, int T)
+__device__ __forceinline__ MemLds mem_carve(char *base, int T, bool cache)
 {
     const int wave = uni((int)(threadIdx.x >> 6));
-    char *p = base + (size_t)wave * mem_lds_bytes(T);
+    char *p = base + (size_t)wave * mem_lds_bytes(T, cache);
     MemLds m;
     m.masks = (uint64_t *)p;
     m.fifo = (int *)(m.masks + T / 64);
-    m.wl.first = m.fifo + 128;
+    m.wl.first = m.fifo + 64 * (FIFO_B + 1);
     m.wl.pref = m.wl.first + 64;
+    m.r2c = (float *)(m.wl.pref + 68);
+    m.rc = r2c_len(T, cache);
     return m;
 }
 
@@ -534,57 +584,122 @@ __device__ __forceinline__ Member member(const Geom &geo, const GroupArg &ga, co
     return M;
 }
 
-// FIFO of neighbour indices; the k-th pushed index is consumed by lane k%64
-struct Fifo {
-    int *buf; // [128]
+// FIFO of neighbour indices; the k-th pushed index is consumed by lane k%64.
+// It holds up to B batches of 64 and hands them to the consumer together, so
+// that the loads of B batches are in flight at once; each lane still adds its
+// terms in push order.  The consumer provides term(j) (loads and arithmetic
+// of one pair) and add(term) (the accumulation).
+template <int B> struct FifoB {
+    int *buf; // [64 * (B + 1)]
     int np;
-    template <class F> __device__ __forceinline__ void push(bool hit, int j, F &consume)
+    template <class F> __device__ __forceinline__ void run(F &f, int cnt)
+    {
+        const int lane = lane_id();
+        typename F::Term t[B];
+        bool v[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const int idx = (b << 6) + lane;
+            v[b] = idx < cnt;
+            if ((b << 6) < cnt) t[b] = f.term(v[b] ? buf[idx] : 0);
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            if ((b << 6) < cnt && v[b]) f.add(t[b]);
+    }
+    template <class F> __device__ __forceinline__ void push(bool hit, int j, F &f)
     {
         const uint64_t m = ballot(hit);
         if (!m) return;
         if (hit) buf[np + mbcnt(m)] = j;
         np = uni(np + popc64(m));
-        if (np >= 64) {
+        if (np >= 64 * B) {
             wave_lds_sync();
+            run(f, 64 * B);
             const int lane = lane_id();
-            consume(buf[lane], true);
-            const int rest = np - 64;
-            int mv = lane < rest ? buf[64 + lane] : 0;
+            const int rest = np - 64 * B;
+            int mv = lane < rest ? buf[64 * B + lane] : 0;
             wave_lds_sync();
             if (lane < rest) buf[lane] = mv;
             np = rest;
         }
     }
-    template <class F> __device__ __forceinline__ void flush(F &consume)
+    template <class F> __device__ __forceinline__ void flush(F &f)
     {
         wave_lds_sync();
-        const int lane = lane_id();
-        if (np > 0) {
-            bool v = lane < np;
-            consume(v ? buf[lane] : 0, v);
-        }
+        if (np > 0) run(f, np);
         np = 0;
         wave_lds_sync();
     }
 };
+typedef FifoB<FIFO_B> Fifo;
+typedef FifoB<2> FifoH; // hydro terms are larger: two batches at a time
 
-// density count pass over the group superset: masks of r2 < h2, their count
+constexpr int UNR = 4; // candidate chunks loaded together
+
+// density count pass over the group superset: masks of r2 < h2, their count.
+// The first pass computes every r2 in FP64 and keeps it, rounded to FP32, for
+// the first S.rc candidates; later passes decide those candidates from the
+// kept value where it is far enough from h2 for the rounding not to matter
+// (relative band 2^-20, far wider than the 2^-24 rounding of both sides) and
+// recompute r2 in FP64 for the rest: the result is exactly that of the FP64
+// test.
 __device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, const Member &M,
-                                          double h2, bool wrap, uint64_t *masks)
+                                          double h2, bool wrap, const MemLds &S, bool first)
 {
     const int lane = lane_id();
     const int nc = M.s.nc;
     const int nch = (nc + 63) >> 6;
     const int32_t *cg = cand + M.s.c0;
+    const bool use_cache = !first && h2 > 1e-30 && h2 < 1e30;
+    const float lo_f = (float)(h2 * (1.0 - 0x1p-20));
+    const float hi_f = (float)(h2 * (1.0 + 0x1p-20));
+    const int cached = use_cache ? min(nch, S.rc >> 6) : 0;
     int cnt = 0;
-    for (int ch = 0; ch < nch; ch++) {
-        const int slot = (ch << 6) + lane;
+    for (int c = 0; c < cached; c++) {
+        const int slot = (c << 6) + lane;
         const bool v = slot < nc;
-        const int j = v ? cg[slot] : 0;
-        const double r2 = r2_of(geo.x[j], geo.y[j], geo.z[j], M.xi, M.yi, M.zi, M.bx.L, wrap);
-        const uint64_t hm = ballot(v && r2 < h2);
-        if (lane == 0) masks[ch] = hm;
+        const float r2f = v ? S.r2c[slot] : 0.0f;
+        bool hit = r2f < lo_f;
+        const bool amb = v && !hit && !(r2f > hi_f);
+        if (ballot(amb)) {
+            if (amb) {
+                const int j = cg[slot];
+                hit = r2_of(geo.x[j], geo.y[j], geo.z[j], M.xi, M.yi, M.zi, M.bx.L, wrap) < h2;
+            }
+        }
+        const uint64_t hm = ballot(v && hit);
+        if (lane == 0) S.masks[c] = hm;
         cnt += popc64(hm);
+    }
+    // the rest: UNR chunks per step, all their loads issued before the tests
+    for (int c0 = cached; c0 < nch; c0 += UNR) {
+        int j[UNR];
+        bool v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const int slot = ((c0 + u) << 6) + lane;
+            v[u] = slot < nc;
+            j[u] = v[u] ? cg[slot] : 0;
+        }
+        double xj[UNR], yj[UNR], zj[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            xj[u] = geo.x[j[u]];
+            yj[u] = geo.y[j[u]];
+            zj[u] = geo.z[j[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const int slot = ((c0 + u) << 6) + lane;
+            const double r2 = r2_of(xj[u], yj[u], zj[u], M.xi, M.yi, M.zi, M.bx.L, wrap);
+            if (first && v[u] && slot < S.rc) S.r2c[slot] = (float)r2;
+            const uint64_t hm = ballot(v[u] && r2 < h2);
+            if (c0 + u < nch) {
+                if (lane == 0) S.masks[c0 + u] = hm;
+                cnt += popc64(hm);
+            }
+        }
     }
     wave_lds_sync();
     return uni(cnt);
@@ -598,13 +713,17 @@ __device__ __forceinline__ void stream_masks(const int32_t *cand, const Member &
     const int lane = lane_id();
     const int nch = (M.s.nc + 63) >> 6;
     const int32_t *cg = cand + M.s.c0;
-    for (int ch = 0; ch < nch; ch++) {
-        uint64_t mk = masks[ch];
-        mk = readlane_u64(mk, 0);
-        if (!mk) continue;
-        const bool hit = (mk >> lane) & 1ull;
-        const int j = hit ? cg[(ch << 6) + lane] : 0;
-        q.push(hit, j, consume);
+    for (int c0 = 0; c0 < nch; c0 += UNR) {
+        uint64_t mk[UNR];
+        int j[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            mk[u] = c0 + u < nch ? readlane_u64(masks[c0 + u], 0) : 0ull;
+            const bool hit = (mk[u] >> lane) & 1ull;
+            j[u] = hit ? cg[((c0 + u) << 6) + lane] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; u++) q.push((mk[u] >> lane) & 1ull, j[u], consume);
     }
     q.flush(consume);
 }
@@ -624,11 +743,11 @@ struct CountVisit {
 };
 
 // filter walked particles against one particle and push the neighbours
-template <int MODE, class F> struct StreamVisit {
+template <int MODE, class F, class Q = Fifo> struct StreamVisit {
     const double *x, *y, *z, *h;
     double xi, yi, zi, L, hi;
     int i;
-    Fifo q;
+    Q q;
     F *consume;
     __device__ bool stop() const { return false; }
     __device__ void operator()(int j, bool valid)
@@ -670,9 +789,11 @@ template <int KER, typename ACC> struct DensPair {
     bool wrap;
     ACC hinv;
     Kahan<ACC> sw, sd;
-    __device__ void operator()(int j, bool valid)
+    struct Term {
+        ACC w, d;
+    };
+    __device__ __forceinline__ Term term(int j) const
     {
-        if (!valid) return;
         double dxd = x[j] - xi, dyd = y[j] - yi, dzd = z[j] - zi;
         if (wrap) {
             dxd = fold(dxd, L);
@@ -685,8 +806,15 @@ template <int KER, typename ACC> struct DensPair {
         ACC w, dw;
         kern_eval<KER, ACC>(q, w, dw);
         ACC mj = (ACC)m[j];
-        sw.add(mj * w);
-        sd.add(mj * mad(q, dw, ACC(3) * w));
+        Term t;
+        t.w = mj * w;
+        t.d = mj * mad(q, dw, ACC(3) * w);
+        return t;
+    }
+    __device__ __forceinline__ void add(const Term &t)
+    {
+        sw.add(t.w);
+        sd.add(t.d);
     }
 };
 
@@ -768,45 +896,93 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
 
 } // namespace
 
+namespace {
+// h iteration on the superset of M: 1 when h is final (in the window, or
+// max_iter evaluations), 0 when h has outgrown the superset (h + d > cov);
+// the masks of the last evaluation stay in LDS
+__device__ __forceinline__ int iterate(const DensK &k, const Member &M, const MemLds &S, double &h,
+                                       double &lo, double &hi, int &it, int &nn, bool &conv)
+{
+    const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
+    bool first = true;
+    while (it < k.max_iter) {
+        if (!(h + M.d <= M.s.cov)) return 0;
+        nn = count_pass(k.g, k.ca.cand, M, h * h, wrap, S, first);
+        first = false;
+        it++;
+        if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
+            conv = true;
+            return 1;
+        }
+        if (it >= k.max_iter) return 1;
+        h = uni_d(h_step(nn, k.n_ngb, k.dn, h, lo, hi));
+        lo = uni_d(lo);
+        hi = uni_d(hi);
+    }
+    return 1;
+}
+
+// A private superset for one particle: one walk with radius `rad` around
+// x_i, straight into a slot of T candidates of the global buffer.  False if
+// the slot or the buffer is too small.
+__device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Member &M, double rad)
+{
+    const int T = k.ga.T;
+    unsigned long long base = 0ull;
+    if (lane_id() == 0) base = atomicAdd(&k.st->cand_top, (unsigned long long)T);
+    base = ((unsigned long long)(uint32_t)uni((int)(uint32_t)base)) |
+           ((unsigned long long)(uint32_t)uni((int)(uint32_t)(base >> 32)) << 32);
+    if (base + (unsigned long long)T > (unsigned long long)k.ca.cap) return false;
+    Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(rad * INFL), 0.0, 0.0, 0};
+    AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + base, T, 0, false, false, B, 0.0};
+    walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, ap, k.st);
+    if (lane_id() == 0) atomicAdd(&k.st->n_walks, 1ull);
+    if (uni_b(ap.over)) return false;
+    M.s.cx = M.xi;
+    M.s.cy = M.yi;
+    M.s.cz = M.zi;
+    M.s.cov = rad;
+    M.s.c0 = (int64_t)base;
+    M.s.nc = uni(ap.n);
+    M.s.flags = GSUP_WRAP;
+    M.d = 0.0;
+    return true;
+}
+} // namespace
+
 // One wave per active particle: h iteration on the group superset, then the
-// density sums.
+// density sums.  A particle whose h outgrows the group superset walks once
+// for a superset of its own, with the bracket's upper end as radius (or 1.25 h
+// while there is none), and iterates on that; only when that fails too does
+// it walk once per h evaluation.
 template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_density(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const MemLds S = mem_carve(lds_raw, k.ga.T);
+    const MemLds S = mem_carve(lds_raw, k.ga.T, true);
     const int A = uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
     for (int a = ar.i; a < ar.end; a += ar.stride) {
-        const Member M = member(k.g, k.ga, k.ca, a);
+        Member M = member(k.g, k.ga, k.ca, a);
         double h = M.h, lo = 0.0, hi = INFINITY;
         int it = 0, nn = 0;
-        bool conv = false, solo = (M.s.flags & GSUP_SOLO) != 0;
-        const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
-        if (!solo) {
-            for (int pass = 0; pass <= k.max_iter; pass++) {
-                if (!(h + M.d <= M.s.cov)) {
-                    solo = true;
-                    break;
-                }
-                nn = count_pass(k.g, k.ca.cand, M, h * h, wrap, S.masks);
-                it++;
-                if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
-                    conv = true;
-                    break;
-                }
-                if (it >= k.max_iter) break;
-                h = uni_d(h_step(nn, k.n_ngb, k.dn, h, lo, hi));
-                lo = uni_d(lo);
-                hi = uni_d(hi);
-                if (pass == k.max_iter) guard_hit(k.st);
+        bool conv = false, done = false;
+        bool usable = (M.s.flags & GSUP_SOLO) == 0;
+        for (int round = 0; round < 4; round++) {
+            if (usable && iterate(k, M, S, h, lo, hi, it, nn, conv)) {
+                done = true;
+                break;
             }
+            if (round == 0 && lane_id() == 0) atomicAdd(&k.st->n_deferred, 1ull);
+            if (round == 3) break;
+            const double rad = hi < INFINITY ? hi : 1.25 * h;
+            usable = own_superset(k, S, M, rad);
+            if (!usable) break;
         }
-        if (solo) {
-            if (lane_id() == 0) atomicAdd(&k.st->n_deferred, 1ull);
+        if (!done) {
             dens_solo<KER, ACC>(k, S, M, h, lo, hi, it);
             continue;
         }
-        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, wrap);
+        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, (M.s.flags & GSUP_WRAP) != 0);
         Fifo q{S.fifo, 0};
         stream_masks(k.ca.cand, M, S.masks, q, pp);
         dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp);
@@ -834,9 +1010,11 @@ template <int KER, typename ACC> struct HydroPair {
     ACC hinv, hinv4, vx, vy, vz, rho, pf, cs;
     Kahan<ACC> ax, ay, az, du;
     ACC vmax;
-    __device__ void operator()(int j, bool valid)
+    struct Term {
+        ACC ax, ay, az, du, vs;
+    };
+    __device__ __forceinline__ Term term(int j) const
     {
-        if (!valid) return;
         constexpr ACC C = (ACC)knorm<KER>();
         double dxd = xi - k->g.x[j], dyd = yi - k->g.y[j], dzd = zi - k->g.z[j];
         if (wrap) {
@@ -887,11 +1065,21 @@ template <int KER, typename ACC> struct HydroPair {
         ACC visc = -(ACC)k->alpha * vsig * wij / (rho + rhoj);
         ACC fac = mj * (pf * dWi + pfj * dWj + visc * dWb);
         ACC fr = fac * rinv;
-        ax.add(-fr * dx);
-        ay.add(-fr * dy);
-        az.add(-fr * dz);
-        du.add(mj * (pf * dWi + ACC(0.5) * visc * dWb) * vr * rinv);
-        vmax = vsig > vmax ? vsig : vmax;
+        Term t;
+        t.ax = -fr * dx;
+        t.ay = -fr * dy;
+        t.az = -fr * dz;
+        t.du = mj * (pf * dWi + ACC(0.5) * visc * dWb) * vr * rinv;
+        t.vs = vsig;
+        return t;
+    }
+    __device__ __forceinline__ void add(const Term &t)
+    {
+        ax.add(t.ax);
+        ay.add(t.ay);
+        az.add(t.az);
+        du.add(t.du);
+        vmax = t.vs > vmax ? t.vs : vmax;
     }
 };
 
@@ -967,7 +1155,7 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
 template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const MemLds S = mem_carve(lds_raw, k.ga.T);
+    const MemLds S = mem_carve(lds_raw, k.ga.T, false);
     const int lane = lane_id();
     const int A = uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
@@ -976,8 +1164,8 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
         if (M.s.flags & GSUP_SOLO) {
             if (lane == 0) atomicAdd(&k.st->n_deferred, 1ull);
             HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
-            StreamVisit<1, HydroPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
-                                                   M.bx.L, M.h, M.i, Fifo{S.fifo, 0}, &hp};
+            StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
+                                                   M.bx.L, M.h, M.i, FifoH{S.fifo, 0}, &hp};
             Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
             walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, sv, k.st);
             if (lane == 0) atomicAdd(&k.st->n_walks, 1ull);
@@ -987,17 +1175,33 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
         }
         const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
         HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, wrap);
-        Fifo q{S.fifo, 0};
+        FifoH q{S.fifo, 0};
         const int nc = M.s.nc;
         const int nch = (nc + 63) >> 6;
         const int32_t *cg = k.ca.cand + M.s.c0;
-        for (int ch = 0; ch < nch; ch++) {
-            const int slot = (ch << 6) + lane;
-            const bool v = slot < nc;
-            const int j = v ? cg[slot] : 0;
-            const double r2 = r2_of(k.g.x[j], k.g.y[j], k.g.z[j], M.xi, M.yi, M.zi, M.bx.L, wrap);
-            const double hm = fmax(M.h, k.g.h[j]);
-            q.push(v && j != M.i && r2 < hm * hm, j, hp);
+        for (int c0 = 0; c0 < nch; c0 += UNR) {
+            int j[UNR];
+            bool v[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                const int slot = ((c0 + u) << 6) + lane;
+                v[u] = slot < nc;
+                j[u] = v[u] ? cg[slot] : 0;
+            }
+            double xj[UNR], yj[UNR], zj[UNR], hj[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                xj[u] = k.g.x[j[u]];
+                yj[u] = k.g.y[j[u]];
+                zj[u] = k.g.z[j[u]];
+                hj[u] = k.g.h[j[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                const double r2 = r2_of(xj[u], yj[u], zj[u], M.xi, M.yi, M.zi, M.bx.L, wrap);
+                const double hm = fmax(M.h, hj[u]);
+                q.push(v[u] && j[u] != M.i && r2 < hm * hm, j[u], hp);
+            }
         }
         q.flush(hp);
         hydro_write<KER, ACC>(k, M.i, hp);
@@ -1088,7 +1292,7 @@ struct VerVisit {
 __global__ __launch_bounds__(256) void k_verify(VerK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const MemLds S = mem_carve(lds_raw, k.ga.T);
+    const MemLds S = mem_carve(lds_raw, k.ga.T, false);
     const int lane = lane_id();
     const int mode = k.ver.mode;
     const int A = uni(*k.ga.n_act);
@@ -1201,7 +1405,7 @@ constexpr int MEM_WAVES = 4; // member waves per workgroup
 hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
                        SearchBufs &sb, DevStatus *st, int T, double skin, int hydro)
 {
-    k_reset_top<<<1, 64, 0, s>>>(st);
+    k_reset_pass<<<1, 64, 0, s>>>(st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     WalkK k;
@@ -1237,7 +1441,7 @@ hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, con
     k.dn = dp.dn;
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
-    const size_t lds = MEM_WAVES * mem_lds_bytes(dp.t_cand);
+    const size_t lds = MEM_WAVES * mem_lds_bytes(dp.t_cand, true);
     const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;
     if (dp.kernel == 0 && dp.accum == SFC_ACCUM_F32)
@@ -1277,7 +1481,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
-    const size_t lds = MEM_WAVES * mem_lds_bytes(hp.t_cand);
+    const size_t lds = MEM_WAVES * mem_lds_bytes(hp.t_cand, false);
     const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;
     if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32)
@@ -1301,6 +1505,6 @@ hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, cons
     k.ver = v;
     k.orig = p.orig;
     k.st = st;
-    return launch_persistent(k_verify, s, k, 64 * MEM_WAVES, MEM_WAVES * mem_lds_bytes(t_cand),
+    return launch_persistent(k_verify, s, k, 64 * MEM_WAVES, MEM_WAVES * mem_lds_bytes(t_cand, false),
                              sb.cu_count, p.n);
 }
