@@ -17,7 +17,6 @@ host cores.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -29,12 +28,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# wave64 VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
+VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 # algorithmic bytes per candidate record and per active (x, y, z FP64 + m FP32;
 # hydro adds h FP64 and v, rho, P f/rho^2, c FP32) and per active particle of
 # inputs read plus outputs written
 DENS_BC, DENS_BIO = 28, 52
 HYD_BC, HYD_BIO = 60, 84
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lognormal_2m.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_lognormal_2m.json")
 
 
 def bench_config():
@@ -47,11 +48,8 @@ def bench_config():
 
 
 def _src_hash():
-    h = hashlib.sha256()
-    for f in ("search.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_1810_09898_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1810_09898_amd.profsum import src_hash
+    return src_hash()
 
 
 def _events():
@@ -180,7 +178,9 @@ def main():
         }
         del ung
 
-    # roofline of the dominant kernel (algorithmic bytes / launch time)
+    # roofline of the dominant call (algorithmic bytes / its device time):
+    # density = walk kernel + per-particle filter/sum kernel; hydro = record
+    # kernel + max-h refit + walk kernel + per-particle kernel
     dens_bytes = st_d["sum_cand"] * DENS_BC + A * DENS_BIO
     hyd_bytes = st_h["sum_cand"] * HYD_BC + A * HYD_BIO
     if ph["hydro"] >= ph["density"]:
@@ -188,14 +188,22 @@ def main():
     else:
         kname, kbytes, kms = "density", dens_bytes, ph["density"]
     achieved = kbytes / (kms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("src_hash") == _src_hash() and tr.get("kernel") == kname:
-            traffic = tr.get("bytes_per_launch")
+    traffic, valu = None, None
+    if os.path.exists(PMC_FILE):
+        pm = json.load(open(PMC_FILE))
+        call = pm.get("calls", {}).get(kname)
+        if pm.get("src_hash") == _src_hash() and call:
+            traffic = call.get("hbm_bytes")
+            insts = call.get("valu_insts")
+            if insts:
+                valu = {"insts": insts, "achieved": round(insts / (kms * 1e-3), 1),
+                        "peak": VALU_PEAK_WAVE_INSTS, "unit": "wave64 VALU insts/s",
+                        "frac": round(insts / (kms * 1e-3) / VALU_PEAK_WAVE_INSTS, 4)}
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-            "algorithmic_bytes": int(kbytes), "launch_ms": round(kms, 4)}
+            "kernels": ("k_walk + k_density" if kname == "density"
+                        else "k_hydro_prep + refit + k_walk + k_hydro"),
+            "algorithmic_bytes": int(kbytes), "launch_ms": round(kms, 4), "valu": valu}
 
     cpu = None
     if not args.no_cpu_baseline:

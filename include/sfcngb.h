@@ -123,7 +123,8 @@ SFC_API int sfc_sort(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out, 
  * the max of their h.  keys: the sorted keys from sfc_sort.  n_leaf >=
  * dims.n_leaf_min. */
 SFC_API int tree_build(sfc_ctx *ctx, const sfc_particles *p, const uint64_t *keys, int32_t n_leaf);
-/* Recompute every node's max h (after density changed h). */
+/* Recompute every node's max h from p->h (hydro_force and the hydro
+ * verify pass do this themselves). */
 SFC_API int tree_refit_hmax(sfc_ctx *ctx, const sfc_particles *p);
 
 /* ---------------------------------------------------------------------- */
@@ -198,12 +199,18 @@ typedef struct {
 
 /* Density pass over the active particles of the last group_ngb_search
  * (sections "Phases of Neighbour Search" and "Adaptive Neighbour
- * Recycling"): each group walks once, every member iterates its h on the
- * group's candidate superset (integer neighbour counts, see the design
- * notes for the step rule), members whose h outgrows the superset finish on
- * their own walk, then
+ * Recycling"): each group walks the octree once (ball R_g + skin * max h
+ * around its first member) and keeps the candidate superset; every member
+ * iterates its h on that superset with integer neighbour counts n = |{j :
+ * r_ij < h}|: stop when |n - n_ngb| <= dn or after max_iter evaluations,
+ * otherwise narrow a bracket (lo = h if n is low, hi = h if high) and move
+ * to h * g, g two Halley steps for (n_ngb/n)^(1/3), or to the bracket's
+ * midpoint when h * g leaves it.  A member whose h outgrows the superset
+ * walks once for a superset of its own.  Then
  *   rho_i = sum_j m_j W(r_ij, h_i),  drho/dh_i,  f_i = 1/(1 + h_i/(3 rho_i) drho/dh_i)
- * are written to p->h, p->rho, p->fgrad and `out` at the active slots. */
+ * are written to p->h, p->rho, p->fgrad and `out` at the active slots.
+ * Uses the candidate buffer of the workspace; the tree's max h is left as it
+ * was (hydro_force refreshes it). */
 SFC_API int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp,
             sfc_density_out *out);
 
@@ -223,7 +230,9 @@ typedef struct {
 /* Hydro force over the active particles of the last group_ngb_search:
  * neighbours j != i closer than max(h_i, h_j) (section "Phases of Neighbour
  * Search"); SPH pressure force with artificial viscosity in the Gadget-2
- * form.  Requires vx, vy, vz, u, rho, fgrad. */
+ * form.  Requires vx, vy, vz, u, rho, fgrad.  First recomputes every node's
+ * max h from p->h (h may have changed since the tree was built), then each
+ * group walks once with R_g + max(max member h, h_j). */
 SFC_API int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp,
                 sfc_hydro_out *out);
 

@@ -124,6 +124,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     tb.start = b.take<uint32_t>(n + 1);
     TreeDev td;
     td.info = b.take<int4>(cap);
+    td.kids = b.take<int32_t>(8 * cap);
     td.lo = b.take<double4>(cap);
     td.hi = b.take<double4>(cap);
     td.parent = b.take<int32_t>(cap);
@@ -376,6 +377,10 @@ int group_ngb_search(sfc_ctx *ctx, const sfc_particles *p, const sfc_group_param
     if (e != hipSuccess) return hip_fail(ctx, e, "groups");
     ctx->have_groups = 1;
     if (verify) {
+        if (verify->mode == 1) {
+            e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
+            if (e != hipSuccess) return hip_fail(ctx, e, "verify refit");
+        }
         e = launch_verify(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, *verify, t_cand, ctx->st);
         if (e != hipSuccess) return hip_fail(ctx, e, "verify");
     }
@@ -404,10 +409,7 @@ int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp, sfc_de
     else memset(&a.out, 0, sizeof(a.out));
     PartDev pd = part_dev(p);
     hipError_t e = launch_density(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "density");
-    // the hydro walk reads every node's max h: refresh it
-    e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
-    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "density refit");
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "density");
 }
 
 int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp,
@@ -433,7 +435,10 @@ int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp
     a.hp = *hp;
     a.out = *out;
     PartDev pd = part_dev(p);
-    hipError_t e = launch_hydro(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
+    // the hydro walk reads every node's max h: refresh it from the current h
+    hipError_t e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hydro_force refit");
+    e = launch_hydro(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
     return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "hydro_force");
 }
 

@@ -141,6 +141,7 @@ struct GSup {
 // ------------------------------------------------------- tree view
 struct TreeDev {
     int4 *info;     // first, count, skip, level | leaf << 8
+    int32_t *kids;  // [8 * capacity]: children of a node in order, -1 past the last
     double4 *lo;    // min x, min y, min z, hmax
     double4 *hi;    // max x, max y, max z, 0
     int32_t *parent;

@@ -126,6 +126,7 @@ struct Geom {
     const double *box_L;
     const int4 *info;
     const double4 *lo, *hi;
+    const int32_t *kids;
     const int32_t *box_root;
     int nb;
 };
@@ -229,8 +230,15 @@ struct WalkLds {
     int *pref;  // [66]
 };
 
+// position (and h) of a walked particle
+struct Pos {
+    double x, y, z, h;
+};
+
 // Leaves `vl` (lane mask) of the current window: flatten their particles and
-// hand them to `visit` 64 at a time, ascending.
+// hand them to `visit` 64 at a time, ascending.  Two batches per step: their
+// lane -> particle searches and their loads (visit.fetch) overlap before
+// visit.take consumes them in order.
 template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4 inf, WalkLds wl, V &visit)
 {
     const int lane = lane_id();
@@ -250,22 +258,28 @@ template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4
     }
     const int nl = popc64(vl);
     wave_lds_sync();
-    for (int t0 = 0; t0 < total; t0 += 64) {
-        int q = t0 + lane;
-        bool valid = q < total;
-        int j = 0;
-        if (valid) {
+    for (int t0 = 0; t0 < total; t0 += 128) {
+        const bool two = t0 + 64 < total;
+        int q[2], j[2];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int qc = min(t0 + 64 * u + lane, total - 1); // clamped: no divergence
+            q[u] = t0 + 64 * u + lane;
             int lo = 0, hi = nl;
 #pragma unroll
             for (int s = 0; s < 7; s++) { // nl <= 64: at most 6 halvings
                 if (hi - lo > 1) {
                     int mid = (lo + hi) >> 1;
-                    if (wl.pref[mid] <= q) lo = mid; else hi = mid;
+                    if (wl.pref[mid] <= qc) lo = mid; else hi = mid;
                 }
             }
-            j = wl.first[lo] + (q - wl.pref[lo]);
+            j[u] = wl.first[lo] + (qc - wl.pref[lo]);
         }
-        visit(j, valid);
+        const Pos p0 = visit.fetch(j[0]);
+        Pos p1 = p0;
+        if (two) p1 = visit.fetch(j[1]);
+        visit.take(j[0], q[0] < total, p0);
+        if (two) visit.take(j[1], q[1] < total, p1);
     }
     wave_lds_sync();
 }
@@ -294,12 +308,48 @@ __device__ __forceinline__ int wave_incl_max(int v)
 // the window start, hence open).  The next window starts at the larger of
 // k + 64 and the largest skip link of a closed node in the window: every
 // node in between is hidden.  Each window advances k by at least 64.
+// does the ball reach node c's bounding box (hydro: with the node's max h)?
+__device__ __forceinline__ bool node_open(const Geom &g, int c, const Ball &B)
+{
+    const double4 lo = g.lo[c], hi = g.hi[c];
+    const double gx = axis_gap(B.cx, lo.x, hi.x, B.L);
+    const double gy = axis_gap(B.cy, lo.y, hi.y, B.L);
+    const double gz = axis_gap(B.cz, lo.z, hi.z, B.L);
+    const double d2 = gx * gx + gy * gy + gz * gz;
+    const double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, lo.w)) * INFL) : B.W2;
+    return d2 < lim;
+}
+
+// Entry node of a walk: from the root, step down while exactly one child of
+// the current node is reached by the ball; every node the ball reaches then
+// lies in the entry node's subtree, [entry, skip(entry)).  Lanes 0-7 test the
+// children of the current node together.
+__device__ __forceinline__ int walk_entry(const Geom &g, int root, const Ball &B)
+{
+    const int lane = lane_id();
+    int p = root;
+#pragma unroll 1
+    for (int d = 0; d < 24; d++) { // 21 key levels below a root
+        const int4 ip = g.info[p];
+        if (ip.w >> 8) break;
+        const int c = lane < 8 ? g.kids[8 * (int64_t)p + lane] : -1;
+        const bool open = c >= 0 && node_open(g, c, B);
+        const uint64_t m = ballot(open);
+        if (popc64(m) != 1) break;
+        const int nc = uni(readlane_i(c, ctz64(m)));
+        if (nc <= p) break; // a child always follows its parent
+        p = nc;
+    }
+    return p;
+}
+
 template <class V>
 __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkLds wl, V &visit,
                      DevStatus *st)
 {
     const int lane = lane_id();
-    int k = uni(root);
+    int k = uni(walk_entry(g, uni(root), B));
+    if (k != root) root_end = min(uni(root_end), uni(g.info[k].z));
     root_end = uni(root_end);
     int steps = 0;
     const int max_steps = (root_end - k) / 64 + 2;
@@ -315,13 +365,7 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkL
         bool open = false;
         if (inr) {
             inf = g.info[node];
-            double4 lo = g.lo[node], hi = g.hi[node];
-            double gx = axis_gap(B.cx, lo.x, hi.x, B.L);
-            double gy = axis_gap(B.cy, lo.y, hi.y, B.L);
-            double gz = axis_gap(B.cz, lo.z, hi.z, B.L);
-            double d2 = gx * gx + gy * gy + gz * gz;
-            double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, lo.w)) * INFL) : B.W2;
-            open = d2 < lim;
+            open = node_open(g, node, B);
         }
         const int hide = (inr && !open) ? inf.z : -1;
         const int incl = wave_incl_max(hide);
@@ -363,15 +407,24 @@ struct AppendCand {
     Ball B;
     double ext;
     __device__ bool stop() const { return over; }
-    __device__ void operator()(int j, bool valid)
+    __device__ __forceinline__ Pos fetch(int j) const
+    {
+        Pos p;
+        p.x = x[j];
+        p.y = y[j];
+        p.z = z[j];
+        p.h = B.hydro ? h[j] : 0.0;
+        return p;
+    }
+    __device__ void take(int j, bool valid, const Pos &p)
     {
         bool keep = false, fl = false;
         double e = 0.0;
         if (valid) {
-            double rx = x[j] - B.cx, ry = y[j] - B.cy, rz = z[j] - B.cz;
+            double rx = p.x - B.cx, ry = p.y - B.cy, rz = p.z - B.cz;
             double dx = fold(rx, B.L), dy = fold(ry, B.L), dz = fold(rz, B.L);
             double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-            double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, h[j])) * INFL) : B.W2;
+            double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, p.h)) * INFL) : B.W2;
             keep = r2 < lim;
             fl = (dx != rx) | (dy != ry) | (dz != rz);
             e = fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
@@ -672,15 +725,20 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, 
         if (lane == 0) S.masks[c] = hm;
         cnt += popc64(hm);
     }
-    // the rest: UNR chunks per step, all their loads issued before the tests
+    // the rest: UNR chunks per step, all their loads issued before the tests,
+    // and the candidate indices of the next step loaded while this one is
+    // tested (loads are unconditional, on clamped slots, so they go out
+    // together)
+    int jn[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; u++) jn[u] = cg[min(((cached + u) << 6) + lane, nc - 1)];
     for (int c0 = cached; c0 < nch; c0 += UNR) {
         int j[UNR];
         bool v[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; u++) {
-            const int slot = ((c0 + u) << 6) + lane;
-            v[u] = slot < nc;
-            j[u] = v[u] ? cg[slot] : 0;
+            v[u] = ((c0 + u) << 6) + lane < nc;
+            j[u] = jn[u];
         }
         double xj[UNR], yj[UNR], zj[UNR];
 #pragma unroll
@@ -689,6 +747,8 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, 
             yj[u] = geo.y[j[u]];
             zj[u] = geo.z[j[u]];
         }
+#pragma unroll
+        for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
 #pragma unroll
         for (int u = 0; u < UNR; u++) {
             const int slot = ((c0 + u) << 6) + lane;
@@ -719,8 +779,7 @@ __device__ __forceinline__ void stream_masks(const int32_t *cand, const Member &
 #pragma unroll
         for (int u = 0; u < UNR; u++) {
             mk[u] = c0 + u < nch ? readlane_u64(masks[c0 + u], 0) : 0ull;
-            const bool hit = (mk[u] >> lane) & 1ull;
-            j[u] = hit ? cg[((c0 + u) << 6) + lane] : 0;
+            j[u] = cg[min(((c0 + u) << 6) + lane, M.s.nc - 1)];
         }
 #pragma unroll
         for (int u = 0; u < UNR; u++) q.push((mk[u] >> lane) & 1ull, j[u], consume);
@@ -734,10 +793,19 @@ struct CountVisit {
     double xi, yi, zi, L, h2;
     int cnt;
     __device__ bool stop() const { return false; }
-    __device__ void operator()(int j, bool valid)
+    __device__ __forceinline__ Pos fetch(int j) const
     {
-        bool hit = false;
-        if (valid) hit = r2_of(x[j], y[j], z[j], xi, yi, zi, L, true) < h2;
+        Pos p;
+        p.x = x[j];
+        p.y = y[j];
+        p.z = z[j];
+        p.h = 0.0;
+        return p;
+    }
+    __device__ void take(int j, bool valid, const Pos &p)
+    {
+        (void)j;
+        const bool hit = valid && r2_of(p.x, p.y, p.z, xi, yi, zi, L, true) < h2;
         cnt = uni(cnt + popc64(ballot(hit)));
     }
 };
@@ -750,15 +818,24 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
     Q q;
     F *consume;
     __device__ bool stop() const { return false; }
-    __device__ void operator()(int j, bool valid)
+    __device__ __forceinline__ Pos fetch(int j) const
+    {
+        Pos p;
+        p.x = x[j];
+        p.y = y[j];
+        p.z = z[j];
+        p.h = MODE == 1 ? h[j] : 0.0;
+        return p;
+    }
+    __device__ void take(int j, bool valid, const Pos &p)
     {
         bool hit = false;
         if (valid) {
-            double r2 = r2_of(x[j], y[j], z[j], xi, yi, zi, L, true);
+            double r2 = r2_of(p.x, p.y, p.z, xi, yi, zi, L, true);
             if (MODE == 0) {
                 hit = r2 < hi * hi;
             } else {
-                double hm = fmax(hi, h[j]);
+                double hm = fmax(hi, p.h);
                 hit = (j != i) && (r2 < hm * hm);
             }
         }
@@ -1179,14 +1256,16 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
         const int nc = M.s.nc;
         const int nch = (nc + 63) >> 6;
         const int32_t *cg = k.ca.cand + M.s.c0;
+        int jn[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) jn[u] = cg[min((u << 6) + lane, nc - 1)];
         for (int c0 = 0; c0 < nch; c0 += UNR) {
             int j[UNR];
             bool v[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-                const int slot = ((c0 + u) << 6) + lane;
-                v[u] = slot < nc;
-                j[u] = v[u] ? cg[slot] : 0;
+                v[u] = ((c0 + u) << 6) + lane < nc;
+                j[u] = jn[u];
             }
             double xj[UNR], yj[UNR], zj[UNR], hj[UNR];
 #pragma unroll
@@ -1196,6 +1275,8 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
                 zj[u] = k.g.z[j[u]];
                 hj[u] = k.g.h[j[u]];
             }
+#pragma unroll
+            for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
                 const double r2 = r2_of(xj[u], yj[u], zj[u], M.xi, M.yi, M.zi, M.bx.L, wrap);
@@ -1270,15 +1351,24 @@ struct VerVisit {
     int i, mode;
     VerifyAcc *va;
     __device__ bool stop() const { return false; }
-    __device__ void operator()(int j, bool valid)
+    __device__ __forceinline__ Pos fetch(int j) const
+    {
+        Pos p;
+        p.x = x[j];
+        p.y = y[j];
+        p.z = z[j];
+        p.h = h[j];
+        return p;
+    }
+    __device__ void take(int j, bool valid, const Pos &p)
     {
         bool hit = false;
         if (valid) {
-            double r2 = r2_of(x[j], y[j], z[j], xi, yi, zi, L, true);
+            double r2 = r2_of(p.x, p.y, p.z, xi, yi, zi, L, true);
             if (mode == 0) {
                 hit = r2 < hi * hi;
             } else {
-                double hm = fmax(hi, h[j]);
+                double hm = fmax(hi, p.h);
                 hit = (j != i) && (r2 < hm * hm);
             }
         }
@@ -1315,7 +1405,7 @@ __global__ __launch_bounds__(256) void k_verify(VerK k)
         for (int ch = 0; ch < nch; ch++) {
             const int slot = (ch << 6) + lane;
             const bool v = slot < nc;
-            const int j = v ? cg[slot] : 0;
+            const int j = cg[min(slot, nc - 1)];
             const double r2 = r2_of(k.g.x[j], k.g.y[j], k.g.z[j], M.xi, M.yi, M.zi, M.bx.L, wrap);
             bool hit;
             if (mode == 0) {
@@ -1344,6 +1434,7 @@ Geom make_geom(const PartDev &p, const TreeDev &t)
     g.info = t.info;
     g.lo = t.lo;
     g.hi = t.hi;
+    g.kids = t.kids;
     g.box_root = t.box_root;
     g.nb = p.nb;
     return g;

@@ -139,92 +139,98 @@ __global__ void k_tree_roots(int nb, const int64_t *__restrict__ box_off,
     if (b == 0) st->n_nodes = (int32_t)start[n];
 }
 
-__global__ void k_tree_nchild(const TreeDev t, const DevStatus *st)
+// child count and child table of node id (children follow each other by
+// skip links: the first is id + 1, the next one starts where a subtree ends)
+__device__ __forceinline__ void tree_children(const TreeDev &t, int id, int nn)
 {
-    int id = blockIdx.x * blockDim.x + threadIdx.x;
-    int nn = min(st->n_nodes, t.capacity);
-    if (id >= nn) return;
     int4 inf = t.info[id];
     int k = 0;
+    int kid[8];
+#pragma unroll
+    for (int s = 0; s < 8; s++) kid[s] = -1;
     if (!(inf.w >> 8)) {
         int c = id + 1;
         int end = min(inf.z, nn);
-        while (c < end) {
+        while (c < end && k < 8) { // the children follow each other by skip links
+            kid[k] = c;
             k++;
             c = t.info[c].z;
         }
     }
     t.nchild[id] = k;
     t.counter[id] = 0;
+    int4 *kp = (int4 *)(t.kids + 8 * (int64_t)id);
+    kp[0] = make_int4(kid[0], kid[1], kid[2], kid[3]);
+    kp[1] = make_int4(kid[4], kid[5], kid[6], kid[7]);
 }
 
-// leaves: reduce their particles; then climb while this thread is the last
-// child to arrive at the parent.
-__global__ void k_tree_up(const PartDev p, const TreeDev t, const DevStatus *st_in,
-                          DevStatus *st, int with_bbox)
+__global__ void k_tree_nchild(const TreeDev t, const DevStatus *st)
 {
-    int id = blockIdx.x * blockDim.x + threadIdx.x;
-    int nn = min(st_in->n_nodes, t.capacity);
-    if (id >= nn) return;
-    int4 inf = t.info[id];
-    if (!(inf.w >> 8)) return;
-    double4 lo = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-    double4 hi = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
-    double hm = 0.0;
-    int bad = 0;
-    int b = p.nb > 1 ? box_of(p.box_off, p.nb, inf.x) : 0;
-    double L = p.box_L[b];
-    for (int i = inf.x; i < inf.x + inf.y; i++) {
-        double hh = p.h[i];
-        hm = fmax(hm, hh);
-        bad |= !(hh > 0.0);
-        if (with_bbox) {
-            double x = p.x[i], y = p.y[i], z = p.z[i];
-            lo.x = fmin(lo.x, x); hi.x = fmax(hi.x, x);
-            lo.y = fmin(lo.y, y); hi.y = fmax(hi.y, y);
-            lo.z = fmin(lo.z, z); hi.z = fmax(hi.z, z);
-            bad |= !(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L);
-        }
-    }
-    if (bad) atomicOr(&st->flags, SFC_ST_BAD_INPUT);
-    if (with_bbox) {
-        lo.w = hm;
-        t.lo[id] = lo;
-        t.hi[id] = hi;
-    } else {
-        t.lo[id].w = hm;
-    }
-    int k = id;
-    for (;;) {
-        int par = t.parent[k];
-        if (par < 0) break;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        int old = __hip_atomic_fetch_add(&t.counter[par], 1, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-        if (old != t.nchild[par] - 1) break;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        int4 pin = t.info[par];
-        double4 plo = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-        double4 phi = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
-        double phm = 0.0;
-        int cend = min(pin.z, nn);
-        for (int c = par + 1; c < cend; c = t.info[c].z) {
-            double4 clo = t.lo[c];
-            phm = fmax(phm, clo.w);
-            if (with_bbox) {
-                double4 chi = t.hi[c];
-                plo.x = fmin(plo.x, clo.x); plo.y = fmin(plo.y, clo.y); plo.z = fmin(plo.z, clo.z);
-                phi.x = fmax(phi.x, chi.x); phi.y = fmax(phi.y, chi.y); phi.z = fmax(phi.z, chi.z);
+    const int nn = min(st->n_nodes, t.capacity);
+    const int stride = gridDim.x * blockDim.x;
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < nn; id += stride)
+        tree_children(t, id, nn);
+}
+
+
+// one level of the bottom-up pass: every node of `level` reduces its
+// particles (leaf) or its children (one level deeper, done by the previous
+// launch).  Levels go from the deepest to the root, one launch each, so no
+// node waits on another inside a kernel.
+__global__ void k_tree_level(const PartDev p, const TreeDev t, const DevStatus *st_in,
+                             DevStatus *st, int with_bbox, int level)
+{
+    const int nn = min(st_in->n_nodes, t.capacity);
+    const int stride = gridDim.x * blockDim.x;
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < nn; id += stride) {
+        const int4 inf = t.info[id];
+        if ((inf.w & 255) != level) continue;
+        double4 lo = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+        double4 hi = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
+        double hm = 0.0;
+        if (inf.w >> 8) {
+            int bad = 0;
+            const int b = p.nb > 1 ? box_of(p.box_off, p.nb, inf.x) : 0;
+            const double L = p.box_L[b];
+            const int i1 = inf.x + inf.y;
+#pragma unroll 4
+            for (int i = inf.x; i < i1; i++) {
+                double hh = p.h[i];
+                hm = fmax(hm, hh);
+                bad |= !(hh > 0.0);
+                if (with_bbox) {
+                    double x = p.x[i], y = p.y[i], z = p.z[i];
+                    lo.x = fmin(lo.x, x); hi.x = fmax(hi.x, x);
+                    lo.y = fmin(lo.y, y); hi.y = fmax(hi.y, y);
+                    lo.z = fmin(lo.z, z); hi.z = fmax(hi.z, z);
+                    bad |= !(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L);
+                }
+            }
+            if (bad) atomicOr(&st->flags, SFC_ST_BAD_INPUT);
+        } else {
+            const int4 *kp = (const int4 *)(t.kids + 8 * (int64_t)id);
+            const int4 ka = kp[0], kb = kp[1];
+            const int kid[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+#pragma unroll
+            for (int s = 0; s < 8; s++) {
+                const int c = kid[s];
+                if (c < 0 || c >= nn) continue;
+                const double4 clo = t.lo[c];
+                hm = fmax(hm, clo.w);
+                if (with_bbox) {
+                    const double4 chi = t.hi[c];
+                    lo.x = fmin(lo.x, clo.x); lo.y = fmin(lo.y, clo.y); lo.z = fmin(lo.z, clo.z);
+                    hi.x = fmax(hi.x, chi.x); hi.y = fmax(hi.y, chi.y); hi.z = fmax(hi.z, chi.z);
+                }
             }
         }
         if (with_bbox) {
-            plo.w = phm;
-            t.lo[par] = plo;
-            t.hi[par] = phi;
+            lo.w = hm;
+            t.lo[id] = lo;
+            t.hi[id] = hi;
         } else {
-            t.lo[par].w = phm;
+            t.lo[id].w = hm;
         }
-        k = par;
     }
 }
 
@@ -254,10 +260,17 @@ hipError_t launch_tree_refit(hipStream_t s, const PartDev &p, TreeDev &t, bool b
                              DevStatus *st, int64_t n)
 {
     (void)n;
-    unsigned gnodes = (unsigned)((t.capacity + 255) / 256);
-    k_tree_nchild<<<gnodes, 256, 0, s>>>(t, st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_tree_up<<<gnodes, 256, 0, s>>>(p, t, st, st, bbox ? 1 : 0);
-    return hipGetLastError();
+    // grid-stride kernels over the nodes (their number is known on the device only)
+    int64_t g = (t.capacity + 255) / 256;
+    const unsigned gnodes = (unsigned)(g < 2048 ? g : 2048);
+    hipError_t e;
+    if (bbox) { // a new tree: child counts and the child table
+        k_tree_nchild<<<gnodes, 256, 0, s>>>(t, st);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (int level = SFC_KEY_BITS; level >= 0; level--) {
+        k_tree_level<<<gnodes, 256, 0, s>>>(p, t, st, st, bbox ? 1 : 0, level);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }

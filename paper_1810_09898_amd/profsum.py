@@ -1,0 +1,157 @@
+"""Summaries of rocprofv3 output for the benchmark's kernels.
+
+    python -m paper_1810_09898_amd.profsum trace DB OUT.txt --cmd "..."
+        kernel-trace statistics (rocpd database, top_kernels view) as text.
+
+    python -m paper_1810_09898_amd.profsum pmc OUT.json --cmd "..." \\
+        --calib-fetch DIR --calib-write DIR RUN_DIR [RUN_DIR ...]
+        per-call counter totals from `rocprofv3 --pmc ... --output-format csv`
+        runs of bench.py.  FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are
+        scaled by the reading of a plain copy of known size (calib.py) to give
+        HBM bytes.  A "call" is one library entry point: density = the walk
+        and the per-particle kernel; hydro_force = the max-h refit, the record
+        kernel, the walk and the per-particle kernel.  The source hash of the
+        search kernels is stored so that the numbers are dropped once the
+        kernels change.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 1 << 30
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("search.hip", "internal.h"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def trace(db: str, out: str, cmd: str) -> str:
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select name, total_calls, total_duration, average, percentage "
+                          "from top_kernels"))
+    lines = [f"# command: {cmd}",
+             "# rocprofv3 kernel trace (top_kernels view of the rocpd database); microseconds",
+             f"{'calls':>6} {'total_us':>12} {'avg_us':>10} {'pct':>6}  kernel"]
+    for name, calls, tot, avg, pct in rows:
+        if pct < 0.01:
+            continue
+        lines.append(f"{calls:6d} {tot:12.1f} {avg:10.1f} {pct:6.2f}  {name[:110]}")
+    txt = "\n".join(lines) + "\n"
+    with open(out, "w") as fh:
+        fh.write(txt)
+    return txt
+
+
+def _csv(d: str):
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    return list(csv.DictReader(open(f[0])))
+
+
+def _dispatches(rows):
+    """dispatch id -> (kernel short name, {counter: value})"""
+    out = collections.OrderedDict()
+    for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
+        d = int(r["Dispatch_Id"])
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").split("<")[0]
+        out.setdefault(d, (name, {}))[1][r["Counter_Name"]] = float(r["Counter_Value"])
+    return out
+
+
+def _calls(disp):
+    """split the dispatch sequence into density and hydro_force calls"""
+    items = list(disp.items())
+    calls = {"density": [], "hydro_force": []}
+    for k, (_, (name, _cs)) in enumerate(items):
+        if name == "k_density":
+            seg = [items[k]]
+            j = k - 1
+            while j >= 0 and items[j][1][0] in ("k_walk", "k_reset_pass") and len(seg) < 3:
+                seg.insert(0, items[j])
+                j -= 1
+            calls["density"].append(seg)
+        if name == "k_hydro":
+            seg = [items[k]]
+            j = k - 1
+            while j >= 0 and items[j][1][0] in ("k_walk", "k_reset_pass", "k_hydro_prep",
+                                                 "k_tree_up", "k_tree_nchild"):
+                seg.insert(0, items[j])
+                j -= 1
+            calls["hydro_force"].append(seg)
+    return calls
+
+
+def pmc(out: str, cmd: str, calib_fetch: str, calib_write: str, runs) -> dict:
+    def copy_reading(d, counter):
+        v = [float(r["Counter_Value"]) for r in _csv(d)
+             if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        return sum(v) / len(v)
+
+    f_fetch = COPY_BYTES / (copy_reading(calib_fetch, "FETCH_SIZE") * 1024)
+    f_write = COPY_BYTES / (copy_reading(calib_write, "WRITE_SIZE") * 1024)
+    per_call = collections.defaultdict(lambda: collections.defaultdict(list))
+    per_kernel = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in runs:
+        disp = _dispatches(_csv(d))
+        for name, cs in disp.values():
+            for c, v in cs.items():
+                per_kernel[name][c].append(v)
+        for call, segs in _calls(disp).items():
+            for seg in segs:
+                tot = collections.Counter()
+                for _, (_, cs) in seg:
+                    tot.update(cs)
+                for c, v in tot.items():
+                    per_call[call][c].append(v)
+    res = {"src_hash": src_hash(), "command": cmd, "copy_factor_fetch": f_fetch,
+           "copy_factor_write": f_write, "calls": {}, "kernels": {}}
+    for call, cs in per_call.items():
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        e = {k: m[k] for k in sorted(m)}
+        if "FETCH_SIZE" in m and "WRITE_SIZE" in m:
+            e["hbm_bytes"] = m["FETCH_SIZE"] * 1024 * f_fetch + m["WRITE_SIZE"] * 1024 * f_write
+        if "SQ_INSTS_VALU" in m:
+            e["valu_insts"] = m["SQ_INSTS_VALU"]
+        res["calls"][call] = e
+    for k, cs in per_kernel.items():
+        res["kernels"][k] = {c: sum(v) / len(v) for c, v in sorted(cs.items())}
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("out")
+    t.add_argument("--cmd", required=True)
+    p = sub.add_parser("pmc")
+    p.add_argument("out")
+    p.add_argument("--cmd", required=True)
+    p.add_argument("--calib-fetch", required=True)
+    p.add_argument("--calib-write", required=True)
+    p.add_argument("runs", nargs="+")
+    a = ap.parse_args()
+    if a.what == "trace":
+        print(trace(a.db, a.out, a.cmd))
+    else:
+        print(json.dumps(pmc(a.out, a.cmd, a.calib_fetch, a.calib_write, a.runs), indent=1))
+
+
+if __name__ == "__main__":
+    main()
