@@ -122,9 +122,13 @@ struct DevStatus {
     unsigned long long sum_cand;
     unsigned long long n_walks;
     unsigned long long sum_iters;
-    unsigned long long cand_top; // bump pointer of the candidate buffer (per pass)
-    int32_t qctr[16];            // per-XCD work counters of the walk kernel (per pass)
-    int32_t pad[6];
+    int32_t pad[2];
+    // Per-pass counters of the search kernels, one per eighth of the work
+    // items, each on its own 128-byte line so that the eighths do not
+    // serialise on one address: bump pointers of the eight regions of the
+    // candidate buffer and the walk kernel's work counters.
+    unsigned long long cand_top[8 * 16]; // cand_top[16 * x]
+    int32_t qctr[8 * 32];                // qctr[32 * x]
 };
 
 // per-group record written by the walk kernel

@@ -116,6 +116,30 @@ __device__ __forceinline__ void guard_hit(DevStatus *st)
     if (lane_id() == 0) atomicOr(&st->flags, (unsigned)SFC_ST_GUARD);
 }
 
+__device__ __forceinline__ unsigned long long uni_u64(unsigned long long v)
+{
+    return ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v)) |
+           ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) << 32);
+}
+
+// Statistics of one wave, added to the status block once, when the wave
+// leaves: a status counter updated by every particle or group would
+// serialise the whole grid on one address.
+struct WaveStats {
+    uint32_t walks = 0, overflow = 0, deferred = 0, iters = 0, not_conv = 0;
+    unsigned long long cand = 0;
+    __device__ __forceinline__ void flush(DevStatus *st) const
+    {
+        if (lane_id() != 0) return;
+        if (walks) atomicAdd(&st->n_walks, (unsigned long long)walks);
+        if (cand) atomicAdd(&st->sum_cand, cand);
+        if (overflow) atomicAdd(&st->n_overflow, (unsigned long long)overflow);
+        if (deferred) atomicAdd(&st->n_deferred, (unsigned long long)deferred);
+        if (iters) atomicAdd(&st->sum_iters, (unsigned long long)iters);
+        if (not_conv) atomicAdd(&st->n_not_converged, (unsigned long long)not_conv);
+    }
+};
+
 } // namespace
 
 // --------------------------------------------------------------- kernel args
@@ -153,7 +177,7 @@ namespace {
 // ranges, so no XCD idles while another has work.  Every take advances a
 // counter, and a wave leaves after all 8 ranges are used up: the loop ends.
 struct Queue {
-    int32_t *ctr; // [8]
+    int32_t *ctr; // [8 * 32]: counter x at ctr[32 * x]
     int n, per, xcd, xs;
 };
 __device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items)
@@ -172,7 +196,7 @@ __device__ __forceinline__ int queue_next(Queue &q)
     while (q.xs < 8) {
         const int x = (q.xcd + q.xs) & 7;
         int t = 0;
-        if (lane_id() == 0) t = atomicAdd(&q.ctr[x], 1);
+        if (lane_id() == 0) t = atomicAdd(&q.ctr[32 * x], 1);
         t = uni(t);
         const int item = x * q.per + t;
         if (t < q.per && item < q.n) return item;
@@ -468,6 +492,18 @@ __device__ __forceinline__ BoxInfo box_info(const Geom &geo, int i)
     return bi;
 }
 
+// Bump allocation of cnt candidates in region x (of 8) of the candidate
+// buffer; -1 when the region is full.
+__device__ __forceinline__ int64_t cand_alloc(DevStatus *st, const CandArg &ca, int x, int cnt)
+{
+    const int64_t rcap = ca.cap >> 3;
+    unsigned long long off = 0ull;
+    if (lane_id() == 0) off = atomicAdd(&st->cand_top[16 * x], (unsigned long long)cnt);
+    off = uni_u64(off);
+    if ((int64_t)off + cnt > rcap) return -1;
+    return (int64_t)x * rcap + (int64_t)off;
+}
+
 } // namespace
 
 // ================================================================== walk kernel
@@ -486,8 +522,10 @@ __global__ void k_reset_pass(DevStatus *st)
 {
     const int t = threadIdx.x;
     if (blockIdx.x != 0) return;
-    if (t == 0) st->cand_top = 0ull;
-    if (t < 16) st->qctr[t] = 0;
+    if (t < 8) {
+        st->cand_top[16 * t] = 0ull;
+        st->qctr[32 * t] = 0;
+    }
 }
 
 // One wave per group: the walk, the superset into the global buffer, the
@@ -501,6 +539,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
     Queue wq = queue_open(k.st->qctr, G);
+    WaveStats ws;
     for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
         const int a = uni(k.ga.goff[g]);
         const int nm = min(uni(k.ga.goff[g + 1]) - a, 64);
@@ -536,14 +575,11 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         if (uni_b(ap.over)) {
             flags = GSUP_SOLO;
         } else {
-            unsigned long long base = 0ull;
-            if (lane == 0) base = atomicAdd(&k.st->cand_top, (unsigned long long)nc);
-            base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base)) |
-                   ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32)) << 32);
-            if (base + (unsigned long long)nc > (unsigned long long)k.ca.cap) {
+            const int64_t base = cand_alloc(k.st, k.ca, g / ((G + 7) >> 3), nc);
+            if (base < 0) {
                 flags = GSUP_SOLO;
             } else {
-                c0 = (int64_t)base;
+                c0 = base;
                 wave_lds_sync();
                 for (int s = lane; s < nc; s += 64) k.ca.cand[c0 + s] = cand[s];
                 if (pair_wrap(uni_b(ap.folded), ap.ext, mfold, mext, bx.L)) flags |= GSUP_WRAP;
@@ -559,13 +595,14 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
             sp.nc = (flags & GSUP_SOLO) ? 0 : nc;
             sp.flags = flags;
             k.ca.sup[g] = sp;
-            atomicAdd(&k.st->n_walks, 1ull);
-            atomicAdd(&k.st->sum_cand, (unsigned long long)nc);
-            if (flags & GSUP_SOLO) atomicAdd(&k.st->n_overflow, 1ull);
         }
+        ws.walks++;
+        ws.cand += (unsigned long long)nc;
+        if (flags & GSUP_SOLO) ws.overflow++;
         if (mem) k.ca.grp[a + lane] = g;
         wave_lds_sync();
     }
+    ws.flush(k.st);
 }
 
 namespace {
@@ -915,8 +952,10 @@ __device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, const Me
 
 template <int KER, typename ACC>
 __device__ void dens_write(const DensK &k, int i, double h, int nn, int it, bool conv,
-                           const DensPair<KER, ACC> &pp)
+                           const DensPair<KER, ACC> &pp, WaveStats &ws)
 {
+    ws.iters += (uint32_t)it;
+    if (!conv) ws.not_conv++;
     double Sw = (double)wave_sum_f_or_d(pp.sw.value());
     double Sd = (double)wave_sum_f_or_d(pp.sd.value());
     if (lane_id() != 0) return;
@@ -935,14 +974,12 @@ __device__ void dens_write(const DensK &k, int i, double h, int nn, int it, bool
     if (k.out.rho64) k.out.rho64[i] = rho;
     if (k.out.drhodh64) k.out.drhodh64[i] = drho;
     if (k.out.fgrad64) k.out.fgrad64[i] = f;
-    atomicAdd(&k.st->sum_iters, (unsigned long long)it);
-    if (!conv) atomicAdd(&k.st->n_not_converged, 1ull);
 }
 
 // one particle on its own: one walk per h evaluation, then the sums
 template <int KER, typename ACC>
 __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, double h, double lo,
-                          double hi, int it)
+                          double hi, int it, WaveStats &ws)
 {
     int nn = 0;
     bool conv = false;
@@ -950,7 +987,7 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
         Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
         CountVisit cv{k.g.x, k.g.y, k.g.z, M.xi, M.yi, M.zi, M.bx.L, h * h, 0};
         walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, cv, k.st);
-        if (lane_id() == 0) atomicAdd(&k.st->n_walks, 1ull);
+        ws.walks++;
         nn = uni(cv.cnt);
         it++;
         if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
@@ -968,7 +1005,8 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
     walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, sv, k.st);
     sv.q.flush(pp);
-    dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp);
+    ws.walks++;
+    dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
 }
 
 } // namespace
@@ -1002,18 +1040,16 @@ __device__ __forceinline__ int iterate(const DensK &k, const Member &M, const Me
 // A private superset for one particle: one walk with radius `rad` around
 // x_i, straight into a slot of T candidates of the global buffer.  False if
 // the slot or the buffer is too small.
-__device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Member &M, double rad)
+__device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Member &M, double rad,
+                                             int region, WaveStats &ws)
 {
     const int T = k.ga.T;
-    unsigned long long base = 0ull;
-    if (lane_id() == 0) base = atomicAdd(&k.st->cand_top, (unsigned long long)T);
-    base = ((unsigned long long)(uint32_t)uni((int)(uint32_t)base)) |
-           ((unsigned long long)(uint32_t)uni((int)(uint32_t)(base >> 32)) << 32);
-    if (base + (unsigned long long)T > (unsigned long long)k.ca.cap) return false;
+    const int64_t base = cand_alloc(k.st, k.ca, region, T);
+    if (base < 0) return false;
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(rad * INFL), 0.0, 0.0, 0};
     AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + base, T, 0, false, false, B, 0.0};
     walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, ap, k.st);
-    if (lane_id() == 0) atomicAdd(&k.st->n_walks, 1ull);
+    ws.walks++;
     if (uni_b(ap.over)) return false;
     M.s.cx = M.xi;
     M.s.cy = M.yi;
@@ -1038,6 +1074,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
     const MemLds S = mem_carve(lds_raw, k.ga.T, true);
     const int A = uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
+    WaveStats ws;
     for (int a = ar.i; a < ar.end; a += ar.stride) {
         Member M = member(k.g, k.ga, k.ca, a);
         double h = M.h, lo = 0.0, hi = INFINITY;
@@ -1049,21 +1086,22 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
                 done = true;
                 break;
             }
-            if (round == 0 && lane_id() == 0) atomicAdd(&k.st->n_deferred, 1ull);
+            if (round == 0) ws.deferred++;
             if (round == 3) break;
             const double rad = hi < INFINITY ? hi : 1.25 * h;
-            usable = own_superset(k, S, M, rad);
+            usable = own_superset(k, S, M, rad, a / ((A + 7) >> 3), ws);
             if (!usable) break;
         }
         if (!done) {
-            dens_solo<KER, ACC>(k, S, M, h, lo, hi, it);
+            dens_solo<KER, ACC>(k, S, M, h, lo, hi, it, ws);
             continue;
         }
         DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, (M.s.flags & GSUP_WRAP) != 0);
         Fifo q{S.fifo, 0};
         stream_masks(k.ca.cand, M, S.masks, q, pp);
-        dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp);
+        dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
     }
+    ws.flush(k.st);
 }
 
 // ================================================================== hydro
@@ -1236,16 +1274,17 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
     const int lane = lane_id();
     const int A = uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
+    WaveStats ws;
     for (int a = ar.i; a < ar.end; a += ar.stride) {
         const Member M = member(k.g, k.ga, k.ca, a);
         if (M.s.flags & GSUP_SOLO) {
-            if (lane == 0) atomicAdd(&k.st->n_deferred, 1ull);
+            ws.deferred++;
             HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
             StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
                                                    M.bx.L, M.h, M.i, FifoH{S.fifo, 0}, &hp};
             Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
             walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, sv, k.st);
-            if (lane == 0) atomicAdd(&k.st->n_walks, 1ull);
+            ws.walks++;
             sv.q.flush(hp);
             hydro_write<KER, ACC>(k, M.i, hp);
             continue;
@@ -1287,6 +1326,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
         q.flush(hp);
         hydro_write<KER, ACC>(k, M.i, hp);
     }
+    ws.flush(k.st);
 }
 
 // ================================================================== verify
