@@ -71,7 +71,7 @@ typedef struct {
     int32_t n_leaf_min;  /* smallest leaf size tree_build will be given (>= 1) */
     int32_t t_cand_max;  /* largest candidate tile any call will use (64..8192, multiple of 64) */
     int32_t cand_per_particle; /* capacity of the candidate buffer that holds every group's
-                                  superset, in candidates per particle (0 = 64; 1..4096).
+                                  superset, in candidates per particle (0 = 96; 1..4096).
                                   Groups that do not fit finish member by member (slower,
                                   same results) and are counted in sfc_status.n_overflow. */
 } sfc_dims;

@@ -176,9 +176,13 @@ namespace {
 // from a counter; when that range is used up it takes items from the other
 // ranges, so no XCD idles while another has work.  Every take advances a
 // counter, and a wave leaves after all 8 ranges are used up: the loop ends.
+// A take hands out QB consecutive items, so the counters see one atomic per
+// QB items.
+constexpr int QB = 1;
 struct Queue {
     int32_t *ctr; // [8 * 32]: counter x at ctr[32 * x]
     int n, per, xcd, xs;
+    int cur, end; // items left of the current take
 };
 __device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items)
 {
@@ -188,18 +192,24 @@ __device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items)
     q.per = (n_items + 7) >> 3;
     q.xcd = blockIdx.x & 7;
     q.xs = 0;
+    q.cur = q.end = 0;
     return q;
 }
 // next item, or -1 when every range is used up
 __device__ __forceinline__ int queue_next(Queue &q)
 {
+    if (q.cur < q.end) return q.cur++;
     while (q.xs < 8) {
         const int x = (q.xcd + q.xs) & 7;
         int t = 0;
-        if (lane_id() == 0) t = atomicAdd(&q.ctr[32 * x], 1);
+        if (lane_id() == 0) t = atomicAdd(&q.ctr[32 * x], QB);
         t = uni(t);
         const int item = x * q.per + t;
-        if (t < q.per && item < q.n) return item;
+        if (t < q.per && item < q.n) {
+            q.cur = item + 1;
+            q.end = min(min(x * q.per + q.per, q.n), item + QB);
+            return item;
+        }
         q.xs++;
     }
     return -1;
@@ -540,6 +550,10 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     const int G = uni(*k.ga.n_groups);
     Queue wq = queue_open(k.st->qctr, G);
     WaveStats ws;
+    // candidates are placed in chunks taken by this wave: up to 8192 slots,
+    // at most a quarter of a wave's fair share of the buffer
+    const int CHUNK = (int)max((int64_t)64, min((int64_t)8192, k.ca.cap / (4 * (int64_t)gridDim.x)));
+    int64_t ck_cur = 0, ck_end = 0;
     for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
         const int a = uni(k.ga.goff[g]);
         const int nm = min(uni(k.ga.goff[g + 1]) - a, 64);
@@ -575,11 +589,18 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         if (uni_b(ap.over)) {
             flags = GSUP_SOLO;
         } else {
-            const int64_t base = cand_alloc(k.st, k.ca, g / ((G + 7) >> 3), nc);
-            if (base < 0) {
+            // the wave's current chunk of the buffer; a new chunk when it is full
+            if (ck_cur + nc > ck_end) {
+                const int csz = max(nc, CHUNK);
+                const int64_t base = cand_alloc(k.st, k.ca, blockIdx.x & 7, csz);
+                ck_cur = base;
+                ck_end = base < 0 ? base : base + csz;
+            }
+            if (ck_cur < 0) {
                 flags = GSUP_SOLO;
             } else {
-                c0 = base;
+                c0 = ck_cur;
+                ck_cur += nc;
                 wave_lds_sync();
                 for (int s = lane; s < nc; s += 64) k.ca.cand[c0 + s] = cand[s];
                 if (pair_wrap(uni_b(ap.folded), ap.ext, mfold, mext, bx.L)) flags |= GSUP_WRAP;

@@ -39,7 +39,8 @@ class StepConfig:
 class Pipeline:
     """Device state of one workload plus the calls of one step."""
 
-    def __init__(self, w, cfg: StepConfig, hydro: bool | None = None, gp_box=None):
+    def __init__(self, w, cfg: StepConfig, hydro: bool | None = None, gp_box=None,
+                 cand_per_particle: int = 0):
         import torch
         self.w = w
         self.cfg = cfg
@@ -51,7 +52,8 @@ class Pipeline:
         self.keys = torch.empty(n, dtype=torch.int64, device=dev)
         t_max = max(cfg.t_cand, cfg.hydro_t_cand)
         t_max = max(64, ((t_max + 63) // 64) * 64)
-        self.ctx = S.Context(n, len(w.box_L), n_leaf_min=min(cfg.n_leaf, 8), t_cand_max=t_max)
+        self.ctx = S.Context(n, len(w.box_L), n_leaf_min=min(cfg.n_leaf, 8), t_cand_max=t_max,
+                             cand_per_particle=cand_per_particle)
         f32 = lambda: torch.zeros(n, dtype=torch.float32, device=dev)  # noqa: E731
         f64 = lambda: torch.zeros(n, dtype=torch.float64, device=dev)  # noqa: E731
         i32 = lambda: torch.zeros(n, dtype=torch.int32, device=dev)  # noqa: E731

@@ -312,6 +312,27 @@ def test_density_independent_of_grouping(policy, cap, f, T, plum, plum_ref):
     assert np.array_equal(b["h"][act], r.h)
 
 
+@pytest.mark.parametrize("cpp,skin", [(1, 1.0), (8, 1.0), (0, 1.3)])
+def test_density_fallback_paths(cpp, skin, plum, plum_ref):
+    """A candidate buffer too small for the group supersets (every member
+    then takes a superset of its own, or walks per h evaluation) and a wider
+    walk skin give the same bits as the default run."""
+    say(f"[density] fallback cand_per_particle={cpp} skin={skin}")
+    ob, s, act, r = plum_ref
+    base = Pipeline(plum, StepConfig(n_group_max=16, t_cand=1024))
+    base.step()
+    pl = Pipeline(plum, StepConfig(n_group_max=16, t_cand=1024, skin=skin), cand_per_particle=cpp)
+    pl.step()
+    _sync()
+    st = pl.ctx.status(raise_on_overflow=False)
+    if cpp == 1:
+        assert st["n_overflow"] > 0 and st["n_deferred"] > 0
+    a, b = base.sorted_numpy(), pl.sorted_numpy()
+    for k in ("h", "rho", "fgrad"):
+        assert np.array_equal(a[k][act], b[k][act]), k
+    assert np.array_equal(b["h"][act], r.h)
+
+
 def test_density_deterministic(plum):
     a = Pipeline(plum, StepConfig())
     a.step()
@@ -353,6 +374,25 @@ def test_hydro_same_inputs(acc, T, logn, logn_hydro_ref):
         err = np.abs(o[k + suf][act] - ref) / A
         assert np.max(err) < tol, (k, np.max(err))
     assert np.max(np.abs(o["vsigmax"][act] / hr.vsigmax - 1)) < 1e-6
+
+
+def test_hydro_fallback_bits(logn):
+    """Hydro with a candidate buffer too small for the group supersets
+    (members walk alone) gives the same bits as the default run."""
+    say("[hydro] fallback cand_per_particle=1")
+    outs, over = [], []
+    for cpp in (0, 1):
+        pl = Pipeline(logn, StepConfig(n_group_max=32), cand_per_particle=cpp)
+        pl.sort()
+        pl.tree()
+        pl.groups()
+        pl.hydro_force()
+        _sync()
+        over.append(pl.ctx.status(raise_on_overflow=False)["n_overflow"])
+        outs.append(pl.outputs_numpy())
+    assert over[1] > over[0]
+    for k in ("ax", "ay", "az", "dudt", "vsigmax"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
 def test_step_end_to_end(logn):
