@@ -248,6 +248,7 @@ struct Ball {
     double W2;     // density: squared walk radius
     double Rg, Hg; // hydro: node radius R_g + max(H_g, node hmax)
     int hydro;
+    int nowrap;    // the ball lies inside the box: no candidate needs the periodic fold
 };
 
 __device__ __forceinline__ double axis_gap(double c, double lo, double hi, double L)
@@ -259,25 +260,23 @@ __device__ __forceinline__ double axis_gap(double c, double lo, double hi, doubl
     return d;
 }
 
-struct WalkLds {
-    int *first; // [64]
-    int *pref;  // [66]
-};
-
 // position (and h) of a walked particle
 struct Pos {
     double x, y, z, h;
 };
 
 // Leaves `vl` (lane mask) of the current window: flatten their particles and
-// hand them to `visit` 64 at a time, ascending.  Two batches per step: their
-// lane -> particle searches and their loads (visit.fetch) overlap before
-// visit.take consumes them in order.
-template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4 inf, WalkLds wl, V &visit)
+// hand them to `visit` 64 at a time, ascending.  A prefix sum of the leaf
+// sizes gives each leaf its first flattened position; in a batch of 64
+// positions only a few leaves start, so each lane finds its leaf by walking
+// the (uniform) list of those starts, and reads the leaf's first particle
+// from the leaf's lane.  Two batches per step: their loads (visit.fetch)
+// overlap before visit.take consumes them in order.
+template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4 inf, V &visit)
 {
     const int lane = lane_id();
-    bool isl = (vl >> lane) & 1ull;
-    int c = isl ? inf.y : 0;
+    const bool isl = (vl >> lane) & 1ull;
+    const int c = isl ? inf.y : 0;
     int incl = c;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -285,37 +284,34 @@ template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4
         if (lane >= o) incl += t;
     }
     const int total = uni(readlane_i(incl, 63));
-    int r = mbcnt(vl);
-    if (isl) {
-        wl.first[r] = inf.x;
-        wl.pref[r] = incl - c;
-    }
-    const int nl = popc64(vl);
-    wave_lds_sync();
+    const int pre = incl - c; // first flattened position of this lane's leaf
+    int carry = 0;            // lane of the leaf covering the position before the batch
     for (int t0 = 0; t0 < total; t0 += 128) {
         const bool two = t0 + 64 < total;
-        int q[2], j[2];
+        int j[2];
 #pragma unroll
         for (int u = 0; u < 2; u++) {
-            const int qc = min(t0 + 64 * u + lane, total - 1); // clamped: no divergence
-            q[u] = t0 + 64 * u + lane;
-            int lo = 0, hi = nl;
-#pragma unroll
-            for (int s = 0; s < 7; s++) { // nl <= 64: at most 6 halvings
-                if (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (wl.pref[mid] <= qc) lo = mid; else hi = mid;
-                }
+            const int b0 = t0 + 64 * u;
+            int own = carry;
+            uint64_t st = ballot(isl && c > 0 && pre >= b0 && pre < b0 + 64);
+            for (int it = 0; it < 65 && st; it++) { // one round per leaf starting here
+                const int ln = ctz64(st);
+                st &= st - 1ull;
+                const int off = uni(readlane_i(pre, ln)) - b0;
+                if (lane >= off) own = ln;
             }
-            j[u] = wl.first[lo] + (qc - wl.pref[lo]);
+            carry = uni(readlane_i(own, 63));
+            const int qc = min(b0 + lane, total - 1); // clamped: no divergence
+            const int f = __shfl(inf.x, own, 64);
+            const int p0 = __shfl(pre, own, 64);
+            j[u] = f + (qc - p0);
         }
         const Pos p0 = visit.fetch(j[0]);
         Pos p1 = p0;
         if (two) p1 = visit.fetch(j[1]);
-        visit.take(j[0], q[0] < total, p0);
-        if (two) visit.take(j[1], q[1] < total, p1);
+        visit.take(j[0], t0 + lane < total, p0);
+        if (two) visit.take(j[1], t0 + 64 + lane < total, p1);
     }
-    wave_lds_sync();
 }
 
 // inclusive prefix maximum over the lanes of a wave
@@ -378,7 +374,7 @@ __device__ __forceinline__ int walk_entry(const Geom &g, int root, const Ball &B
 }
 
 template <class V>
-__device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkLds wl, V &visit,
+__device__ void walk(const Geom &g, int root, int root_end, const Ball &B, V &visit,
                      DevStatus *st)
 {
     const int lane = lane_id();
@@ -409,7 +405,7 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, WalkL
         const uint64_t vl = ballot(on_walk && open && (inf.w >> 8));
         const int far = uni(readlane_i(incl, 63));
         int nk = max(k + 64, far);
-        if (vl) emit_leaves(vl, inf, wl, visit);
+        if (vl) emit_leaves(vl, inf, visit);
         k = uni(min(nk, root_end));
     }
 }
@@ -454,7 +450,18 @@ struct AppendCand {
     {
         bool keep = false, fl = false;
         double e = 0.0;
-        if (valid) {
+        if (B.nowrap) {
+            // the ball lies inside the box: raw differences are the minimum
+            // images of every candidate it can keep (and a particle whose
+            // raw difference is not is farther than the ball radius either
+            // way); `ext` already holds the ball radius
+            if (valid) {
+                const double dx = p.x - B.cx, dy = p.y - B.cy, dz = p.z - B.cz;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                const double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, p.h)) * INFL) : B.W2;
+                keep = r2 < lim;
+            }
+        } else if (valid) {
             double rx = p.x - B.cx, ry = p.y - B.cy, rz = p.z - B.cz;
             double dx = fold(rx, B.L), dy = fold(ry, B.L), dz = fold(rz, B.L);
             double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
@@ -545,7 +552,6 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     extern __shared__ __align__(16) char lds_raw[];
     const int T = k.ga.T;
     int *cand = (int *)lds_raw;
-    WalkLds wl{cand + T, cand + T + 64};
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
     Queue wq = queue_open(k.st->qctr, G);
@@ -580,9 +586,15 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         const double R = uni_d(wave_max_d(d));
         const double H = uni_d(wave_max_d(hi));
         const double cov = k.hydro ? R + H : R + k.skin * H;
-        Ball B{cx, cy, cz, bx.L, sq(cov * INFL), R, H, k.hydro};
-        AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, cand, T, 0, false, false, B, 0.0};
-        walk(k.g, bx.root, bx.root_end, B, wl, ap, k.st);
+        // largest distance a kept candidate can have; the ball needs no
+        // periodic fold when it stays inside the box on every axis
+        const double rad =
+            (k.hydro ? (R + fmax(H, uni_d(k.g.lo[bx.root].w))) * INFL : cov * INFL) * (1.0 + 0x1p-20);
+        const int nowrap = cx - rad >= 0.0 && cx + rad < bx.L && cy - rad >= 0.0 &&
+                           cy + rad < bx.L && cz - rad >= 0.0 && cz + rad < bx.L;
+        Ball B{cx, cy, cz, bx.L, sq(cov * INFL), R, H, k.hydro, nowrap};
+        AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, cand, T, 0, false, false, B, nowrap ? rad : 0.0};
+        walk(k.g, bx.root, bx.root_end, B, ap, k.st);
         const int nc = uni(ap.n);
         int flags = 0;
         int64_t c0 = 0;
@@ -632,7 +644,7 @@ namespace {
 constexpr int FIFO_B = 4; // neighbour batches of 64 consumed together
 
 // LDS of one member wave: neighbour masks of the last filter pass, the FIFO
-// and the walk scratch of the solo path
+// and the squared-distance cache
 // squared distances kept (as FP32) for the first R2C_MAX candidates
 constexpr int R2C_MAX = 1024;
 __host__ __device__ constexpr int r2c_len(int T, bool cache) { return cache ? (T < R2C_MAX ? T : R2C_MAX) : 0; }
@@ -640,14 +652,12 @@ __host__ __device__ constexpr int r2c_len(int T, bool cache) { return cache ? (T
 struct MemLds {
     uint64_t *masks; // [T/64]
     int *fifo;       // [64 * (FIFO_B + 1)]
-    WalkLds wl;      // [64] + [66]
     float *r2c;      // [r2c_len]: squared distances of the first pass
     int rc;
 };
 __host__ __device__ constexpr size_t mem_lds_bytes(int T, bool cache)
 {
-    return (size_t)8 * (T / 64) + (size_t)4 * (64 * (FIFO_B + 1) + 64 + 66 + 2) +
-           (size_t)4 * r2c_len(T, cache);
+    return (size_t)8 * (T / 64) + (size_t)4 * 64 * (FIFO_B + 1) + (size_t)4 * r2c_len(T, cache);
 }
 __device__ __forceinline__ MemLds mem_carve(char *base, int T, bool cache)
 {
@@ -656,9 +666,7 @@ __device__ __forceinline__ MemLds mem_carve(char *base, int T, bool cache)
     MemLds m;
     m.masks = (uint64_t *)p;
     m.fifo = (int *)(m.masks + T / 64);
-    m.wl.first = m.fifo + 64 * (FIFO_B + 1);
-    m.wl.pref = m.wl.first + 64;
-    m.r2c = (float *)(m.wl.pref + 68);
+    m.r2c = (float *)(m.fifo + 64 * (FIFO_B + 1));
     m.rc = r2c_len(T, cache);
     return m;
 }
@@ -1007,7 +1015,7 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
     for (int guard = 0; guard <= k.max_iter; guard++) {
         Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
         CountVisit cv{k.g.x, k.g.y, k.g.z, M.xi, M.yi, M.zi, M.bx.L, h * h, 0};
-        walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, cv, k.st);
+        walk(k.g, M.bx.root, M.bx.root_end, B, cv, k.st);
         ws.walks++;
         nn = uni(cv.cnt);
         it++;
@@ -1024,7 +1032,7 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
     StreamVisit<0, DensPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi, M.bx.L, h, M.i,
                                           Fifo{S.fifo, 0}, &pp};
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
-    walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, sv, k.st);
+    walk(k.g, M.bx.root, M.bx.root_end, B, sv, k.st);
     sv.q.flush(pp);
     ws.walks++;
     dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
@@ -1069,7 +1077,7 @@ __device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Me
     if (base < 0) return false;
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(rad * INFL), 0.0, 0.0, 0};
     AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + base, T, 0, false, false, B, 0.0};
-    walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, ap, k.st);
+    walk(k.g, M.bx.root, M.bx.root_end, B, ap, k.st);
     ws.walks++;
     if (uni_b(ap.over)) return false;
     M.s.cx = M.xi;
@@ -1304,7 +1312,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
             StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
                                                    M.bx.L, M.h, M.i, FifoH{S.fifo, 0}, &hp};
             Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
-            walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, sv, k.st);
+            walk(k.g, M.bx.root, M.bx.root_end, B, sv, k.st);
             ws.walks++;
             sv.q.flush(hp);
             hydro_write<KER, ACC>(k, M.i, hp);
@@ -1455,7 +1463,7 @@ __global__ __launch_bounds__(256) void k_verify(VerK k)
             VerVisit vv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi, M.bx.L, M.h, M.i, mode, &va};
             Ball B = mode == 0 ? Ball{M.xi, M.yi, M.zi, M.bx.L, sq(M.h * INFL), 0.0, 0.0, 0}
                                : Ball{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
-            walk(k.g, M.bx.root, M.bx.root_end, B, S.wl, vv, k.st);
+            walk(k.g, M.bx.root, M.bx.root_end, B, vv, k.st);
             verify_write(k, M.i, va);
             continue;
         }
@@ -1568,7 +1576,7 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.st = st;
     k.skin = skin;
     k.hydro = hydro;
-    const size_t lds = (size_t)4 * T + 4 * (64 + 66 + 2);
+    const size_t lds = (size_t)4 * T;
     return launch_persistent(k_walk, s, k, 64, lds, sb.cu_count, p.n);
 }
 } // namespace
