@@ -30,7 +30,7 @@ from .pipeline import Pipeline, StepConfig
 F_GRID = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0)
 NG_GRID = (4, 8, 16, 32, 64)
 T_GRID = (1024, 2048, 4096)
-LEAF_GRID = (8, 16, 32)
+LEAF_GRID = (8, 16, 32, 64)
 SKIN_GRID = (1.0, 1.05, 1.1)
 
 CACHE = os.environ.get("SFCNGB_TUNE_CACHE",

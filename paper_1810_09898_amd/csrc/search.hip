@@ -150,7 +150,7 @@ struct Geom {
     const double *box_L;
     const int4 *info;
     const double4 *lo, *hi;
-    const int32_t *kids;
+    const int32_t *kids, *nchild;
     const int32_t *box_root;
     int nb;
 };
@@ -410,6 +410,98 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, V &vi
     }
 }
 
+// Level-by-level walk for the group kernel.  An ordered list of items (in
+// LDS) holds, in pre-order, the leaves reached so far and the internal nodes
+// of the current level that the ball reaches; each round replaces every
+// internal node by its reached children, in order, so the list stays in
+// pre-order.  Only the children of reached nodes are tested (the window walk
+// also tests the nodes hidden below closed ones).  At the end the list holds
+// the reached leaves in ascending particle order, and they are emitted like
+// the window walk emits them, so both walks hand the visitor the same
+// particles in the same order.  Returns false, having emitted nothing, when
+// the list would outgrow its LCAP slots; the caller then takes the window
+// walk.
+constexpr int LCAP = 256;
+
+template <class V>
+__device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int *lb, V &visit)
+{
+    const int lane = lane_id();
+    const int entry = uni(walk_entry(g, uni(root), B));
+    const int4 ie = g.info[entry];
+    if (!uni_b(node_open(g, entry, B))) return true; // the ball reaches nothing
+    if (lane == 0) la[0] = entry | (int)((uint32_t)(ie.w >> 8) << 31);
+    int m = 1;
+    wave_lds_sync();
+    for (int level = 0; level < 24; level++) {
+        int mb = 0;
+        bool inner = false; // an internal node was kept: one more round
+        for (int c0 = 0; c0 < m; c0 += 64) {
+            const int idx = c0 + lane;
+            const bool vi = idx < m;
+            const int it = vi ? la[idx] : 0;
+            const bool lf = it < 0;
+            const int node = it & 0x7fffffff;
+            const int cnt = vi ? (lf ? 1 : g.nchild[node]) : 0;
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                int t = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += t;
+            }
+            const int total = uni(readlane_i(incl, 63));
+            const int pre = incl - cnt;
+            int carry = 0;
+            for (int b0 = 0; b0 < total; b0 += 64) {
+                int own = carry;
+                uint64_t sm = ballot(cnt > 0 && pre >= b0 && pre < b0 + 64);
+                for (int r = 0; r < 65 && sm; r++) {
+                    const int ln = ctz64(sm);
+                    sm &= sm - 1ull;
+                    const int off = uni(readlane_i(pre, ln)) - b0;
+                    if (lane >= off) own = ln;
+                }
+                carry = uni(readlane_i(own, 63));
+                const bool valid = b0 + lane < total;
+                const int oit = __shfl(it, own, 64);
+                const int slot = b0 + lane - __shfl(pre, own, 64);
+                const int onode = oit & 0x7fffffff;
+                int c = onode, cl = 1;
+                bool keep = valid;
+                if (oit >= 0) { // an internal item: test its child `slot`
+                    c = valid ? g.kids[8 * (int64_t)onode + min(max(slot, 0), 7)] : -1;
+                    keep = valid && c >= 0 && node_open(g, c, B);
+                    cl = keep ? (int)(g.info[c].w >> 8) : 1;
+                }
+                const uint64_t km = ballot(keep);
+                if (ballot(keep && !cl)) inner = true;
+                const int nk = popc64(km);
+                if (mb + nk > LCAP) return false;
+                if (keep) lb[mb + mbcnt(km)] = c | (int)((uint32_t)cl << 31);
+                mb = uni(mb + nk);
+            }
+        }
+        wave_lds_sync();
+        int *t = la;
+        la = lb;
+        lb = t;
+        m = mb;
+        if (!uni_b(inner)) break;
+    }
+    // the list now holds leaves only, ascending
+    for (int c0 = 0; c0 < m; c0 += 64) {
+        if (visit.stop()) break;
+        const int idx = c0 + lane;
+        const bool vi = idx < m;
+        int4 inf = make_int4(0, 0, 0, 0);
+        if (vi) inf = g.info[la[idx] & 0x7fffffff];
+        const uint64_t vl = ballot(vi);
+        emit_leaves(vl, inf, visit);
+    }
+    wave_lds_sync();
+    return true;
+}
+
 // canonical squared distance of x_j relative to x_i (fold when `wrap`)
 __device__ __forceinline__ double r2_of(double xj, double yj, double zj, double xi, double yi,
                                         double zi, double L, bool wrap)
@@ -552,6 +644,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     extern __shared__ __align__(16) char lds_raw[];
     const int T = k.ga.T;
     int *cand = (int *)lds_raw;
+    int *lst = cand + T; // [2 * LCAP]: item lists of the level walk
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
     Queue wq = queue_open(k.st->qctr, G);
@@ -594,7 +687,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
                            cy + rad < bx.L && cz - rad >= 0.0 && cz + rad < bx.L;
         Ball B{cx, cy, cz, bx.L, sq(cov * INFL), R, H, k.hydro, nowrap};
         AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, cand, T, 0, false, false, B, nowrap ? rad : 0.0};
-        walk(k.g, bx.root, bx.root_end, B, ap, k.st);
+        if (!walk_levels(k.g, bx.root, B, lst, lst + LCAP, ap)) // list too long: window walk
+            walk(k.g, bx.root, bx.root_end, B, ap, k.st);
         const int nc = uni(ap.n);
         int flags = 0;
         int64_t c0 = 0;
@@ -1504,6 +1598,7 @@ Geom make_geom(const PartDev &p, const TreeDev &t)
     g.lo = t.lo;
     g.hi = t.hi;
     g.kids = t.kids;
+    g.nchild = t.nchild;
     g.box_root = t.box_root;
     g.nb = p.nb;
     return g;
@@ -1576,7 +1671,7 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.st = st;
     k.skin = skin;
     k.hydro = hydro;
-    const size_t lds = (size_t)4 * T;
+    const size_t lds = (size_t)4 * T + (size_t)4 * 2 * LCAP;
     return launch_persistent(k_walk, s, k, 64, lds, sb.cu_count, p.n);
 }
 } // namespace
