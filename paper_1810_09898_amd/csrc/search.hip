@@ -743,15 +743,17 @@ constexpr int FIFO_B = 4; // neighbour batches of 64 consumed together
 constexpr int R2C_MAX = 1024;
 __host__ __device__ constexpr int r2c_len(int T, bool cache) { return cache ? (T < R2C_MAX ? T : R2C_MAX) : 0; }
 
+constexpr int FIFO_BYTES = 64 * 3 * 16; // the larger of 64*(FIFO_B+1) density and 64*3 hydro entries
+
 struct MemLds {
     uint64_t *masks; // [T/64]
-    int *fifo;       // [64 * (FIFO_B + 1)]
+    void *fifo;      // FIFO_BYTES
     float *r2c;      // [r2c_len]: squared distances of the first pass
     int rc;
 };
 __host__ __device__ constexpr size_t mem_lds_bytes(int T, bool cache)
 {
-    return (size_t)8 * (T / 64) + (size_t)4 * 64 * (FIFO_B + 1) + (size_t)4 * r2c_len(T, cache);
+    return (size_t)8 * (T / 64) + (size_t)FIFO_BYTES + (size_t)4 * r2c_len(T, cache);
 }
 __device__ __forceinline__ MemLds mem_carve(char *base, int T, bool cache)
 {
@@ -759,8 +761,8 @@ __device__ __forceinline__ MemLds mem_carve(char *base, int T, bool cache)
     char *p = base + (size_t)wave * mem_lds_bytes(T, cache);
     MemLds m;
     m.masks = (uint64_t *)p;
-    m.fifo = (int *)(m.masks + T / 64);
-    m.r2c = (float *)(m.fifo + 64 * (FIFO_B + 1));
+    m.fifo = (void *)(m.masks + T / 64);
+    m.r2c = (float *)((char *)m.fifo + FIFO_BYTES);
     m.rc = r2c_len(T, cache);
     return m;
 }
@@ -797,14 +799,31 @@ __device__ __forceinline__ Member member(const Geom &geo, const GroupArg &ga, co
     return M;
 }
 
-// FIFO of neighbour indices; the k-th pushed index is consumed by lane k%64.
+// FIFO entries: a neighbour and what the filter already knows of the pair.
+// Density: r^2 rounded to FP32 from the canonical FP64 value.  Hydro: the
+// minimum-image x_i - x_j rounded to FP32.  Every path that pushes a pair
+// computes these the same way, so a particle's sums do not depend on the
+// path (group superset, own superset or own walk).
+struct DEnt {
+    int j;
+    float r2;
+};
+struct HEnt {
+    int j;
+    float dx, dy, dz;
+};
+
+// FIFO of neighbour entries; the k-th pushed entry is consumed by lane k%64.
 // It holds up to B batches of 64 and hands them to the consumer together, so
 // that the loads of B batches are in flight at once; each lane still adds its
-// terms in push order.  The consumer provides term(j) (loads and arithmetic
-// of one pair) and add(term) (the accumulation).
-template <int B> struct FifoB {
-    int *buf; // [64 * (B + 1)]
-    int np;
+// terms in push order.  The consumer provides term(entry) (loads and
+// arithmetic of one pair) and add(term) (the accumulation).
+template <int B, class E> struct FifoB {
+    static constexpr int SIZE = 64 * (B + 1); // ring of SIZE entries
+    E *buf;
+    int np;       // entries held
+    int head = 0; // ring position of the oldest entry
+    __device__ __forceinline__ static int wrap(int i) { return i >= SIZE ? i - SIZE : i; }
     template <class F> __device__ __forceinline__ void run(F &f, int cnt)
     {
         const int lane = lane_id();
@@ -814,27 +833,24 @@ template <int B> struct FifoB {
         for (int b = 0; b < B; b++) {
             const int idx = (b << 6) + lane;
             v[b] = idx < cnt;
-            if ((b << 6) < cnt) t[b] = f.term(v[b] ? buf[idx] : 0);
+            if ((b << 6) < cnt) t[b] = f.term(v[b] ? buf[wrap(head + idx)] : E{});
         }
 #pragma unroll
         for (int b = 0; b < B; b++)
             if ((b << 6) < cnt && v[b]) f.add(t[b]);
     }
-    template <class F> __device__ __forceinline__ void push(bool hit, int j, F &f)
+    template <class F> __device__ __forceinline__ void push(bool hit, const E &e, F &f)
     {
         const uint64_t m = ballot(hit);
         if (!m) return;
-        if (hit) buf[np + mbcnt(m)] = j;
+        if (hit) buf[wrap(wrap(head + np) + mbcnt(m))] = e;
         np = uni(np + popc64(m));
         if (np >= 64 * B) {
             wave_lds_sync();
             run(f, 64 * B);
-            const int lane = lane_id();
-            const int rest = np - 64 * B;
-            int mv = lane < rest ? buf[64 * B + lane] : 0;
+            head = uni(wrap(head + 64 * B));
+            np -= 64 * B;
             wave_lds_sync();
-            if (lane < rest) buf[lane] = mv;
-            np = rest;
         }
     }
     template <class F> __device__ __forceinline__ void flush(F &f)
@@ -842,11 +858,12 @@ template <int B> struct FifoB {
         wave_lds_sync();
         if (np > 0) run(f, np);
         np = 0;
+        head = 0;
         wave_lds_sync();
     }
 };
-typedef FifoB<FIFO_B> Fifo;
-typedef FifoB<2> FifoH; // hydro terms are larger: two batches at a time
+typedef FifoB<FIFO_B, DEnt> Fifo;
+typedef FifoB<2, HEnt> FifoH; // hydro terms are larger: two batches at a time
 
 constexpr int UNR = 4; // candidate chunks loaded together
 
@@ -925,10 +942,11 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, 
     return uni(cnt);
 }
 
-// stream the neighbours recorded in `masks` through the FIFO
+// stream the neighbours recorded in the masks through the FIFO, each with
+// its r^2 (kept by the first pass, or recomputed past the kept range)
 template <class F>
-__device__ __forceinline__ void stream_masks(const int32_t *cand, const Member &M, const uint64_t *masks,
-                                             Fifo &q, F &consume)
+__device__ __forceinline__ void stream_masks(const Geom &geo, const int32_t *cand, const Member &M,
+                                             const MemLds &S, bool wrap, Fifo &q, F &consume)
 {
     const int lane = lane_id();
     const int nch = (M.s.nc + 63) >> 6;
@@ -938,11 +956,20 @@ __device__ __forceinline__ void stream_masks(const int32_t *cand, const Member &
         int j[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; u++) {
-            mk[u] = c0 + u < nch ? readlane_u64(masks[c0 + u], 0) : 0ull;
+            mk[u] = c0 + u < nch ? readlane_u64(S.masks[c0 + u], 0) : 0ull;
             j[u] = cg[min(((c0 + u) << 6) + lane, M.s.nc - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < UNR; u++) q.push((mk[u] >> lane) & 1ull, j[u], consume);
+        for (int u = 0; u < UNR; u++) {
+            const int slot = ((c0 + u) << 6) + lane;
+            float r2f = 0.0f;
+            if ((c0 + u) * 64 < S.rc) {
+                r2f = S.r2c[min(slot, S.rc - 1)];
+            } else if (mk[u]) {
+                r2f = (float)r2_of(geo.x[j[u]], geo.y[j[u]], geo.z[j[u]], M.xi, M.yi, M.zi, M.bx.L, wrap);
+            }
+            q.push((mk[u] >> lane) & 1ull, DEnt{j[u], r2f}, consume);
+        }
     }
     q.flush(consume);
 }
@@ -990,16 +1017,17 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
     __device__ void take(int j, bool valid, const Pos &p)
     {
         bool hit = false;
-        if (valid) {
-            double r2 = r2_of(p.x, p.y, p.z, xi, yi, zi, L, true);
-            if (MODE == 0) {
-                hit = r2 < hi * hi;
-            } else {
-                double hm = fmax(hi, p.h);
-                hit = (j != i) && (r2 < hm * hm);
-            }
+        if constexpr (MODE == 0) {
+            const double r2 = r2_of(p.x, p.y, p.z, xi, yi, zi, L, true);
+            hit = valid && r2 < hi * hi;
+            q.push(hit, DEnt{j, (float)r2}, *consume);
+        } else {
+            const double dx = fold(xi - p.x, L), dy = fold(yi - p.y, L), dz = fold(zi - p.z, L);
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double hm = fmax(hi, p.h);
+            hit = valid && (j != i) && (r2 < hm * hm);
+            q.push(hit, HEnt{j, (float)dx, (float)dy, (float)dz}, *consume);
         }
-        q.push(hit, j, *consume);
     }
 };
 
@@ -1029,16 +1057,15 @@ template <int KER, typename ACC> struct DensPair {
     struct Term {
         ACC w, d;
     };
-    __device__ __forceinline__ Term term(int j) const
+    __device__ __forceinline__ Term term(const DEnt &e) const
     {
-        double dxd = x[j] - xi, dyd = y[j] - yi, dzd = z[j] - zi;
-        if (wrap) {
-            dxd = fold(dxd, L);
-            dyd = fold(dyd, L);
-            dzd = fold(dzd, L);
+        const int j = e.j;
+        ACC r2;
+        if (sizeof(ACC) == 8) { // FP64 variant: r^2 from the coordinates
+            r2 = (ACC)r2_of(x[j], y[j], z[j], xi, yi, zi, L, wrap);
+        } else {
+            r2 = (ACC)e.r2;
         }
-        ACC dx = (ACC)dxd, dy = (ACC)dyd, dz = (ACC)dzd;
-        ACC r2 = mad(dz, dz, mad(dy, dy, dx * dx));
         ACC q = sqrt(r2) * hinv;
         ACC w, dw;
         kern_eval<KER, ACC>(q, w, dw);
@@ -1124,7 +1151,7 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
     }
     DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, true);
     StreamVisit<0, DensPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi, M.bx.L, h, M.i,
-                                          Fifo{S.fifo, 0}, &pp};
+                                          Fifo{(DEnt *)S.fifo, 0}, &pp};
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
     walk(k.g, M.bx.root, M.bx.root_end, B, sv, k.st);
     sv.q.flush(pp);
@@ -1220,8 +1247,8 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
             continue;
         }
         DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, (M.s.flags & GSUP_WRAP) != 0);
-        Fifo q{S.fifo, 0};
-        stream_masks(k.ca.cand, M, S.masks, q, pp);
+        Fifo q{(DEnt *)S.fifo, 0};
+        stream_masks(k.g, k.ca.cand, M, S, (M.s.flags & GSUP_WRAP) != 0, q, pp);
         dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
     }
     ws.flush(k.st);
@@ -1251,16 +1278,26 @@ template <int KER, typename ACC> struct HydroPair {
     struct Term {
         ACC ax, ay, az, du, vs;
     };
-    __device__ __forceinline__ Term term(int j) const
+    __device__ __forceinline__ Term term(const HEnt &e) const
     {
         constexpr ACC C = (ACC)knorm<KER>();
-        double dxd = xi - k->g.x[j], dyd = yi - k->g.y[j], dzd = zi - k->g.z[j];
-        if (wrap) {
-            dxd = fold(dxd, L);
-            dyd = fold(dyd, L);
-            dzd = fold(dzd, L);
+        const int j = e.j;
+        ACC dx, dy, dz;
+        if (sizeof(ACC) == 8) { // FP64 variant: displacement from the coordinates
+            double dxd = xi - k->g.x[j], dyd = yi - k->g.y[j], dzd = zi - k->g.z[j];
+            if (wrap) {
+                dxd = fold(dxd, L);
+                dyd = fold(dyd, L);
+                dzd = fold(dzd, L);
+            }
+            dx = (ACC)dxd;
+            dy = (ACC)dyd;
+            dz = (ACC)dzd;
+        } else {
+            dx = (ACC)e.dx;
+            dy = (ACC)e.dy;
+            dz = (ACC)e.dz;
         }
-        ACC dx = (ACC)dxd, dy = (ACC)dyd, dz = (ACC)dzd;
         ACC mj, vxj, vyj, vzj, rhoj, pfj, csj, hj;
         if (sizeof(ACC) == 8) {
             double gm1 = k->gamma - 1.0;
@@ -1404,7 +1441,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
             ws.deferred++;
             HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
             StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
-                                                   M.bx.L, M.h, M.i, FifoH{S.fifo, 0}, &hp};
+                                                   M.bx.L, M.h, M.i, FifoH{(HEnt *)S.fifo, 0}, &hp};
             Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
             walk(k.g, M.bx.root, M.bx.root_end, B, sv, k.st);
             ws.walks++;
@@ -1414,7 +1451,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
         }
         const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
         HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, wrap);
-        FifoH q{S.fifo, 0};
+        FifoH q{(HEnt *)S.fifo, 0};
         const int nc = M.s.nc;
         const int nch = (nc + 63) >> 6;
         const int32_t *cg = k.ca.cand + M.s.c0;
@@ -1441,9 +1478,16 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
             for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-                const double r2 = r2_of(xj[u], yj[u], zj[u], M.xi, M.yi, M.zi, M.bx.L, wrap);
+                // x_i - x_j (the force direction), folded when pairs need it
+                double dx = M.xi - xj[u], dy = M.yi - yj[u], dz = M.zi - zj[u];
+                if (wrap) {
+                    dx = fold(dx, M.bx.L);
+                    dy = fold(dy, M.bx.L);
+                    dz = fold(dz, M.bx.L);
+                }
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
                 const double hm = fmax(M.h, hj[u]);
-                q.push(v[u] && j[u] != M.i && r2 < hm * hm, j[u], hp);
+                q.push(v[u] && j[u] != M.i && r2 < hm * hm, HEnt{j[u], (float)dx, (float)dy, (float)dz}, hp);
             }
         }
         q.flush(hp);
