@@ -150,6 +150,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     xb.grp = b.take<int32_t>(n);
     xb.pa = b.take<float4>(n);
     xb.pb = b.take<float4>(n);
+    xb.pos4 = b.take<float4>(n);
     xb.cu_count = c ? c->cu : 0;
     if (c && base) {
         c->st = st;

@@ -231,6 +231,7 @@ struct SearchBufs {
     GSup *sup;        // [n] per group
     int32_t *grp;     // [n] per active: its group
     float4 *pa, *pb;  // [n] hydro records: (m, v) and (rho, f P / rho^2, c, h)
+    float4 *pos4;     // [n] density: FP32 x, y, z and m
     int32_t cu_count;
 };
 struct DensityArgs {

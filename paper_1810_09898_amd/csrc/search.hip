@@ -800,7 +800,7 @@ __device__ __forceinline__ Member member(const Geom &geo, const GroupArg &ga, co
 }
 
 // FIFO entries: a neighbour and what the filter already knows of the pair.
-// Density: r^2 rounded to FP32 from the canonical FP64 value.  Hydro: the
+// Density: the FP32 r^2 of the FP32 positions (r2_f32).  Hydro: the
 // minimum-image x_i - x_j rounded to FP32.  Every path that pushes a pair
 // computes these the same way, so a particle's sums do not depend on the
 // path (group superset, own superset or own walk).
@@ -867,31 +867,56 @@ typedef FifoB<2, HEnt> FifoH; // hydro terms are larger: two batches at a time
 
 constexpr int UNR = 4; // candidate chunks loaded together
 
+// Pair r^2 in FP32 from the FP32 copies of the positions (rounded to
+// nearest), folded in FP32 when `wrap`.  Every path that needs a pair's FP32
+// r^2 computes it this way, so the density sums see one value per pair.
+__device__ __forceinline__ float fold32(float d, float L)
+{
+    const float half = 0.5f * L;
+    if (d >= half) d = d - L;
+    else if (d < -half) d = d + L;
+    return d;
+}
+__device__ __forceinline__ float r2_f32(float xj, float yj, float zj, float xi, float yi, float zi,
+                                        float L, bool wrap)
+{
+    float dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    if (wrap) {
+        dx = fold32(dx, L);
+        dy = fold32(dy, L);
+        dz = fold32(dz, L);
+    }
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
 // density count pass over the group superset: masks of r2 < h2, their count.
-// The first pass computes every r2 in FP64 and keeps it, rounded to FP32, for
-// the first S.rc candidates; later passes decide those candidates from the
-// kept value where it is far enough from h2 for the rounding not to matter
-// (relative band 2^-20, far wider than the 2^-24 rounding of both sides) and
-// recompute r2 in FP64 for the rest: the result is exactly that of the FP64
-// test.
-__device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, const Member &M,
-                                          double h2, bool wrap, const MemLds &S, bool first)
+// The test is decided on the FP32 r^2 of the FP32 positions wherever that is
+// safely away from h^2, and on the canonical FP64 r^2 otherwise, so the
+// result is exactly that of the FP64 test.  Bound: each coordinate is off by
+// at most u L (u = 2^-24, coordinates in [0, L)), a (folded) difference by
+// 4 u L + u |d|, so near r = h the FP32 r^2 is within 14 u L h + 5 u h^2 of
+// the FP64 one; the band is E = 16 u (L h + h^2).  The first pass keeps the
+// FP32 r^2 of the first S.rc candidates in LDS for the later passes.
+__device__ __forceinline__ int count_pass(const Geom &geo, const float4 *P, const int32_t *cand,
+                                          const Member &M, double h, bool wrap, const MemLds &S,
+                                          bool first)
 {
     const int lane = lane_id();
     const int nc = M.s.nc;
     const int nch = (nc + 63) >> 6;
     const int32_t *cg = cand + M.s.c0;
-    const bool use_cache = !first && h2 > 1e-30 && h2 < 1e30;
-    const float lo_f = (float)(h2 * (1.0 - 0x1p-20));
-    const float hi_f = (float)(h2 * (1.0 + 0x1p-20));
-    const int cached = use_cache ? min(nch, S.rc >> 6) : 0;
+    const double h2 = h * h;
+    const double E = 0x1p-20 * (M.bx.L * h + h2);
+    const double lo_b = h2 - E, hi_b = h2 + E;
+    const float xf = (float)M.xi, yf = (float)M.yi, zf = (float)M.zi, Lf = (float)M.bx.L;
+    const int cached = first ? 0 : min(nch, S.rc >> 6);
     int cnt = 0;
     for (int c = 0; c < cached; c++) {
         const int slot = (c << 6) + lane;
         const bool v = slot < nc;
-        const float r2f = v ? S.r2c[slot] : 0.0f;
-        bool hit = r2f < lo_f;
-        const bool amb = v && !hit && !(r2f > hi_f);
+        const double r2f = v ? (double)S.r2c[slot] : 0.0;
+        bool hit = r2f < lo_b;
+        const bool amb = v && !hit && !(r2f > hi_b);
         if (ballot(amb)) {
             if (amb) {
                 const int j = cg[slot];
@@ -917,21 +942,25 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, 
             v[u] = ((c0 + u) << 6) + lane < nc;
             j[u] = jn[u];
         }
-        double xj[UNR], yj[UNR], zj[UNR];
+        float4 pj[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; u++) {
-            xj[u] = geo.x[j[u]];
-            yj[u] = geo.y[j[u]];
-            zj[u] = geo.z[j[u]];
-        }
+        for (int u = 0; u < UNR; u++) pj[u] = P[j[u]];
 #pragma unroll
         for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
 #pragma unroll
         for (int u = 0; u < UNR; u++) {
             const int slot = ((c0 + u) << 6) + lane;
-            const double r2 = r2_of(xj[u], yj[u], zj[u], M.xi, M.yi, M.zi, M.bx.L, wrap);
-            if (first && v[u] && slot < S.rc) S.r2c[slot] = (float)r2;
-            const uint64_t hm = ballot(v[u] && r2 < h2);
+            const float r2f = r2_f32(pj[u].x, pj[u].y, pj[u].z, xf, yf, zf, Lf, wrap);
+            if (first && v[u] && slot < S.rc) S.r2c[slot] = r2f;
+            bool hit = (double)r2f < lo_b;
+            const bool amb = v[u] && !hit && !((double)r2f > hi_b);
+            if (ballot(amb)) {
+                if (amb) {
+                    const int jj = j[u];
+                    hit = r2_of(geo.x[jj], geo.y[jj], geo.z[jj], M.xi, M.yi, M.zi, M.bx.L, wrap) < h2;
+                }
+            }
+            const uint64_t hm = ballot(v[u] && hit);
             if (c0 + u < nch) {
                 if (lane == 0) S.masks[c0 + u] = hm;
                 cnt += popc64(hm);
@@ -945,9 +974,10 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const int32_t *cand, 
 // stream the neighbours recorded in the masks through the FIFO, each with
 // its r^2 (kept by the first pass, or recomputed past the kept range)
 template <class F>
-__device__ __forceinline__ void stream_masks(const Geom &geo, const int32_t *cand, const Member &M,
+__device__ __forceinline__ void stream_masks(const float4 *P, const int32_t *cand, const Member &M,
                                              const MemLds &S, bool wrap, Fifo &q, F &consume)
 {
+    const float xf = (float)M.xi, yf = (float)M.yi, zf = (float)M.zi, Lf = (float)M.bx.L;
     const int lane = lane_id();
     const int nch = (M.s.nc + 63) >> 6;
     const int32_t *cg = cand + M.s.c0;
@@ -966,7 +996,8 @@ __device__ __forceinline__ void stream_masks(const Geom &geo, const int32_t *can
             if ((c0 + u) * 64 < S.rc) {
                 r2f = S.r2c[min(slot, S.rc - 1)];
             } else if (mk[u]) {
-                r2f = (float)r2_of(geo.x[j[u]], geo.y[j[u]], geo.z[j[u]], M.xi, M.yi, M.zi, M.bx.L, wrap);
+                const float4 pj = P[j[u]];
+                r2f = r2_f32(pj.x, pj.y, pj.z, xf, yf, zf, Lf, wrap);
             }
             q.push((mk[u] >> lane) & 1ull, DEnt{j[u], r2f}, consume);
         }
@@ -1020,7 +1051,9 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
         if constexpr (MODE == 0) {
             const double r2 = r2_of(p.x, p.y, p.z, xi, yi, zi, L, true);
             hit = valid && r2 < hi * hi;
-            q.push(hit, DEnt{j, (float)r2}, *consume);
+            const float r2f = r2_f32((float)p.x, (float)p.y, (float)p.z, (float)xi, (float)yi,
+                                     (float)zi, (float)L, true);
+            q.push(hit, DEnt{j, r2f}, *consume);
         } else {
             const double dx = fold(xi - p.x, L), dy = fold(yi - p.y, L), dz = fold(zi - p.z, L);
             const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
@@ -1038,6 +1071,7 @@ struct DensK {
     Geom g;
     GroupArg ga;
     CandArg ca;
+    const float4 *pos4; // FP32 x, y, z and m per particle
     const float *m;
     float *rho, *fgrad;
     sfc_density_out out;
@@ -1172,7 +1206,7 @@ __device__ __forceinline__ int iterate(const DensK &k, const Member &M, const Me
     bool first = true;
     while (it < k.max_iter) {
         if (!(h + M.d <= M.s.cov)) return 0;
-        nn = count_pass(k.g, k.ca.cand, M, h * h, wrap, S, first);
+        nn = count_pass(k.g, k.pos4, k.ca.cand, M, h, wrap, S, first);
         first = false;
         it++;
         if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
@@ -1248,7 +1282,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
         }
         DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, (M.s.flags & GSUP_WRAP) != 0);
         Fifo q{(DEnt *)S.fifo, 0};
-        stream_masks(k.g, k.ca.cand, M, S, (M.s.flags & GSUP_WRAP) != 0, q, pp);
+        stream_masks(k.pos4, k.ca.cand, M, S, (M.s.flags & GSUP_WRAP) != 0, q, pp);
         dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
     }
     ws.flush(k.st);
@@ -1409,6 +1443,15 @@ __device__ void hydro_write(const HydroK &k, int i, const HydroPair<KER, ACC> &h
     if (k.out.dudt64) k.out.dudt64[i] = du;
 }
 } // namespace
+
+__global__ void k_dens_prep(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                            const double *__restrict__ z, const float *__restrict__ m,
+                            float4 *__restrict__ pos4)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], m[i]);
+}
 
 __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float *__restrict__ vx,
                              const float *__restrict__ vy, const float *__restrict__ vz,
@@ -1724,13 +1767,17 @@ hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, con
                           SearchBufs &sb, const DensityArgs &a, DevStatus *st)
 {
     const sfc_density_params &dp = a.dp;
-    hipError_t e = launch_walk(s, p, t, g, sb, st, dp.t_cand, dp.skin, 0);
+    k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.m, sb.pos4);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_walk(s, p, t, g, sb, st, dp.t_cand, dp.skin, 0);
     if (e != hipSuccess) return e;
     DensK k;
     memset(&k, 0, sizeof(k));
     k.g = make_geom(p, t);
     k.ga = make_groups(g, dp.t_cand);
     k.ca = make_cand(sb);
+    k.pos4 = sb.pos4;
     k.m = p.m;
     k.rho = p.rho;
     k.fgrad = p.fgrad;
