@@ -799,6 +799,19 @@ __device__ __forceinline__ Member member(const Geom &geo, const GroupArg &ga, co
     return M;
 }
 
+// The walk of one particle inside the per-particle kernels: level by level
+// with its item lists in the squared-distance cache (idle during the walk),
+// the window walk when that cache is too small or the lists overflow.  Both
+// give the same particles in the same order.
+template <class V>
+__device__ __forceinline__ void solo_walk(const Geom &g, const MemLds &S, const Member &M,
+                                          const Ball &B, V &visit, DevStatus *st)
+{
+    int *lst = (int *)S.r2c;
+    if (S.rc >= 2 * LCAP && walk_levels(g, M.bx.root, B, lst, lst + LCAP, visit)) return;
+    walk(g, M.bx.root, M.bx.root_end, B, visit, st);
+}
+
 // FIFO entries: a neighbour and what the filter already knows of the pair.
 // Density: the FP32 r^2 of the FP32 positions (r2_f32).  Hydro: the
 // minimum-image x_i - x_j rounded to FP32.  Every path that pushes a pair
@@ -1232,7 +1245,7 @@ __device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Me
     if (base < 0) return false;
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(rad * INFL), 0.0, 0.0, 0};
     AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + base, T, 0, false, false, B, 0.0};
-    walk(k.g, M.bx.root, M.bx.root_end, B, ap, k.st);
+    solo_walk(k.g, S, M, B, ap, k.st);
     ws.walks++;
     if (uni_b(ap.over)) return false;
     M.s.cx = M.xi;
