@@ -83,10 +83,8 @@ int64_t sort_tiles(const sfc_dims &d) { return (d.n + 4095) / 4096; }
 
 int64_t cand_capacity(const sfc_dims &d)
 {
-    int64_t per = d.cand_per_particle > 0 ? d.cand_per_particle : 96;
-    int64_t c = per * d.n + 64 * (int64_t)d.t_cand_max;
-    const int64_t lim = ((int64_t)1 << 31) - 1;
-    return c < lim ? c : lim;
+    const int64_t per = d.cand_per_particle > 0 ? d.cand_per_particle : 96;
+    return per * d.n + 64 * (int64_t)d.t_cand_max;
 }
 
 bool dims_ok(const sfc_dims *d)

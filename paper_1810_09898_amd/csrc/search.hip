@@ -606,11 +606,17 @@ __device__ __forceinline__ BoxInfo box_info(const Geom &geo, int i)
 __device__ __forceinline__ int64_t cand_alloc(DevStatus *st, const CandArg &ca, int x, int cnt)
 {
     const int64_t rcap = ca.cap >> 3;
-    unsigned long long off = 0ull;
-    if (lane_id() == 0) off = atomicAdd(&st->cand_top[16 * x], (unsigned long long)cnt);
-    off = uni_u64(off);
-    if ((int64_t)off + cnt > rcap) return -1;
-    return (int64_t)x * rcap + (int64_t)off;
+    // the own region first, then the others: a region fills up before the
+    // rest where its XCD took more than its share of the work
+#pragma unroll 1
+    for (int t = 0; t < 8; t++) {
+        const int r = (x + t) & 7;
+        unsigned long long off = 0ull;
+        if (lane_id() == 0) off = atomicAdd(&st->cand_top[16 * r], (unsigned long long)cnt);
+        off = uni_u64(off);
+        if ((int64_t)off + cnt <= rcap) return (int64_t)r * rcap + (int64_t)off;
+    }
+    return -1;
 }
 
 } // namespace
@@ -1089,6 +1095,7 @@ struct DensK {
     float *rho, *fgrad;
     sfc_density_out out;
     DevStatus *st;
+    int64_t priv; // offset in the candidate buffer of the private slots (T per wave), -1: none
     int n_ngb, dn, max_iter, fixed_h;
 };
 
@@ -1235,14 +1242,17 @@ __device__ __forceinline__ int iterate(const DensK &k, const Member &M, const Me
 }
 
 // A private superset for one particle: one walk with radius `rad` around
-// x_i, straight into a slot of T candidates of the global buffer.  False if
-// the slot or the buffer is too small.
+// x_i, straight into the wave's private slot of T candidates (a fixed area
+// behind the group supersets, reused particle after particle: a private
+// superset is dead once its particle is done).  False if the slot is too
+// small or there are no slots.
 __device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Member &M, double rad,
-                                             int region, WaveStats &ws)
+                                             WaveStats &ws)
 {
     const int T = k.ga.T;
-    const int64_t base = cand_alloc(k.st, k.ca, region, T);
-    if (base < 0) return false;
+    if (k.priv < 0) return false;
+    const int wave = (int)blockIdx.x * (int)(blockDim.x >> 6) + uni((int)(threadIdx.x >> 6));
+    const int64_t base = k.priv + (int64_t)wave * T;
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(rad * INFL), 0.0, 0.0, 0};
     AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + base, T, 0, false, false, B, 0.0};
     solo_walk(k.g, S, M, B, ap, k.st);
@@ -1286,7 +1296,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
             if (round == 0) ws.deferred++;
             if (round == 3) break;
             const double rad = hi < INFINITY ? hi : 1.25 * h;
-            usable = own_superset(k, S, M, rad, a / ((A + 7) >> 3), ws);
+            usable = own_superset(k, S, M, rad, ws);
             if (!usable) break;
         }
         if (!done) {
@@ -1776,20 +1786,39 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
 }
 } // namespace
 
-hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
-                          SearchBufs &sb, const DensityArgs &a, DevStatus *st)
+namespace {
+// The density pass: the walk of the groups, then k_density on a persistent
+// grid.  Each wave of that grid owns a private slot of T candidates at the end
+// of the buffer (when the slots take at most half of it); the group supersets
+// use the rest.
+template <int KER, typename ACC>
+hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                       const SearchBufs &sb, const DensityArgs &a, DevStatus *st)
 {
     const sfc_density_params &dp = a.dp;
+    const size_t lds = MEM_WAVES * mem_lds_bytes(dp.t_cand, true);
+    const int th = 64 * MEM_WAVES;
+    auto kern = k_density<KER, ACC>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const unsigned grid = grid_size(kern, th, lds, sb.cu_count, p.n);
+    const int64_t priv = (int64_t)grid * MEM_WAVES * dp.t_cand;
+    SearchBufs gs = sb;
+    if (priv <= sb.cand_cap / 2) gs.cand_cap = sb.cand_cap - priv;
     k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.m, sb.pos4);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_walk(s, p, t, g, sb, st, dp.t_cand, dp.skin, 0);
+    e = launch_walk(s, p, t, g, gs, st, dp.t_cand, dp.skin, 0);
     if (e != hipSuccess) return e;
     DensK k;
     memset(&k, 0, sizeof(k));
     k.g = make_geom(p, t);
     k.ga = make_groups(g, dp.t_cand);
-    k.ca = make_cand(sb);
+    k.ca = make_cand(gs);
+    k.priv = gs.cand_cap < sb.cand_cap ? gs.cand_cap : -1;
     k.pos4 = sb.pos4;
     k.m = p.m;
     k.rho = p.rho;
@@ -1800,15 +1829,19 @@ hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, con
     k.dn = dp.dn;
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
-    const size_t lds = MEM_WAVES * mem_lds_bytes(dp.t_cand, true);
-    const int th = 64 * MEM_WAVES;
-    const int64_t n = p.n;
-    if (dp.kernel == 0 && dp.accum == SFC_ACCUM_F32)
-        return launch_persistent(k_density<0, float>, s, k, th, lds, sb.cu_count, n);
-    if (dp.kernel == 0) return launch_persistent(k_density<0, double>, s, k, th, lds, sb.cu_count, n);
-    if (dp.accum == SFC_ACCUM_F32)
-        return launch_persistent(k_density<1, float>, s, k, th, lds, sb.cu_count, n);
-    return launch_persistent(k_density<1, double>, s, k, th, lds, sb.cu_count, n);
+    kern<<<grid, th, lds, s>>>(k);
+    return hipGetLastError();
+}
+} // namespace
+
+hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
+                          SearchBufs &sb, const DensityArgs &a, DevStatus *st)
+{
+    const sfc_density_params &dp = a.dp;
+    if (dp.kernel == 0 && dp.accum == SFC_ACCUM_F32) return run_density<0, float>(s, p, t, g, sb, a, st);
+    if (dp.kernel == 0) return run_density<0, double>(s, p, t, g, sb, a, st);
+    if (dp.accum == SFC_ACCUM_F32) return run_density<1, float>(s, p, t, g, sb, a, st);
+    return run_density<1, double>(s, p, t, g, sb, a, st);
 }
 
 hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,

@@ -10,6 +10,7 @@ inputs, so repeated steps do identical work.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass, field, replace
 
 import numpy as np
@@ -40,8 +41,14 @@ class Pipeline:
     """Device state of one workload plus the calls of one step."""
 
     def __init__(self, w, cfg: StepConfig, hydro: bool | None = None, gp_box=None,
-                 cand_per_particle: int = 0):
+                 cand_per_particle: int | None = None):
+        """cand_per_particle: capacity of the superset buffer per particle; by
+        default 1.5 N_ngb per active particle (an ungrouped pass fits), at
+        least 96."""
         import torch
+        if cand_per_particle is None:
+            per_act = 1.5 * w.n_ngb * float(np.count_nonzero(w.state["active"])) / max(w.n, 1)
+            cand_per_particle = int(min(4096, max(96, math.ceil(per_act) + 16)))
         self.w = w
         self.cfg = cfg
         self.hydro = w.hydro if hydro is None else hydro

@@ -87,7 +87,7 @@ def _calls(disp):
             seg = [items[k]]
             j = k - 1
             while j >= 0 and items[j][1][0] in ("k_walk", "k_reset_pass", "k_hydro_prep",
-                                                 "k_tree_up", "k_tree_nchild"):
+                                                 "k_tree_level", "k_tree_nchild"):
                 seg.insert(0, items[j])
                 j -= 1
             calls["hydro_force"].append(seg)

@@ -31,6 +31,14 @@ from dataclasses import dataclass, field
 import numpy as np
 
 QUANT = 2.0 ** -24
+# when set, the slow generation steps report their progress on stderr
+VERBOSE = False
+
+
+def _say(msg):
+    if VERBOSE:
+        import sys
+        print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 @dataclass
@@ -147,6 +155,7 @@ def initial_h(rng, x, y, z, n_ngb, perturb=0.1, chunk=1 << 18):
     d = np.empty(len(x))
     for s in range(0, len(x), chunk):
         d[s:s + chunk] = tree.query(p[s:s + chunk], k=[n_ngb], workers=-1)[0][:, 0]
+        _say(f"initial h: {min(s + chunk, len(x))}/{len(x)}")
     del tree, p
     h = d * (1.0 + rng.uniform(-perturb, perturb, len(x)))
     nd = n_ngb / (4.0 / 3.0 * math.pi * h ** 3)
@@ -259,6 +268,7 @@ def plummer_batch(n_boxes=64, seed0=1000, n_range=(1e4, 5e5), n_ngb=64, dn=2,
         nb = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
         x, y, z = plummer_mixture(rng, nb)
         h, nd = initial_h(rng, x, y, z, n_ngb)
+        _say(f"box {b + 1}/{n_boxes}: {nb} particles")
         st = _state(x, y, z, h, nd, nb)
         frac = rng.uniform(0.01, 1.0)
         st["active"] = active_cells(rng, x, y, z, frac, run_mean)
