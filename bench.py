@@ -43,7 +43,7 @@ def bench_config():
     the 2M lognormal workload)."""
     from paper_1810_09898_amd.pipeline import StepConfig
     from paper_1810_09898_amd import sfcngb as S
-    return StepConfig(n_leaf=32, policy=S.POLICY_PAPER, n_group_max=36, f=0.6, chunk=1024,
+    return StepConfig(n_leaf=128, policy=S.POLICY_PAPER, n_group_max=24, f=0.5, chunk=1024,
                       t_cand=2048, hydro_t_cand=2048, skin=1.0)
 
 

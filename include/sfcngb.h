@@ -108,7 +108,8 @@ typedef struct {
  * the Gadget3 Performance"; Hilbert variant: Skilling's transpose algorithm,
  * 21 bits per axis, cell = floor(x/L * 2^21) clamped).  Out of place: every
  * non-NULL array of `in` is gathered into the same array of `out` in sorted
- * order (equal keys keep input order).  out->orig receives in->orig permuted,
+ * order (equal keys keep input order); out->active receives 1 where
+ * in->active is nonzero, else 0.  out->orig receives in->orig permuted,
  * or the input index if in->orig is NULL.  keys_out: device [n], the sorted
  * keys.  perm_out: device [n] or NULL, the input index of each output slot.
  * in and out must not alias. */

@@ -28,9 +28,9 @@ from . import sfcngb as S
 from .pipeline import Pipeline, StepConfig
 
 F_GRID = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0)
-NG_GRID = (4, 8, 16, 32, 64)
+NG_GRID = (4, 8, 16, 24, 32, 48, 64)
 T_GRID = (1024, 2048, 4096)
-LEAF_GRID = (8, 16, 32, 64)
+LEAF_GRID = (8, 16, 32, 64, 128, 256)
 SKIN_GRID = (1.0, 1.05, 1.1)
 
 CACHE = os.environ.get("SFCNGB_TUNE_CACHE",
@@ -174,8 +174,18 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="lognormal_hydro")
     ap.add_argument("--rounds", type=int, default=2)
+    ap.add_argument("--bins", default="0",
+                    help="timestep bins to tune one after the other (workloads with state['bin']: "
+                         "bin b = the particles whose deepest bin is >= b are active)")
     args = ap.parse_args()
+    W.VERBOSE = True
     w = W.WORKLOADS[args.workload]()
-    print("prior", asdict(prior(w)), flush=True)
-    best, c, seen = tune(w, rounds=args.rounds, log=lambda s: print(s, flush=True))
-    print("best", asdict(best), c, flush=True)
+    base = dict(w.state)
+    for b in [int(v) for v in args.bins.split(",")]:
+        if "bin" in base:
+            w.state = dict(base)
+            w.state["active"] = (base["bin"] >= b).astype(np.uint8)
+        print(f"workload {args.workload} bin {b}: {w.n_active} active", flush=True)
+        print("prior", asdict(prior(w)), flush=True)
+        best, c, seen = tune(w, rounds=args.rounds, log=lambda s: print(s, flush=True))
+        print("best", asdict(best), c, flush=True)

@@ -103,6 +103,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     int64_t nt = sort_tiles(d);
     DevStatus *st = b.take<DevStatus>(1);
     SortBufs sb;
+    sb.rec = b.take<PRec>(n);
     sb.key_a = b.take<uint64_t>(n);
     sb.key_b = b.take<uint64_t>(n);
     sb.val_a = b.take<uint32_t>(n);
@@ -297,7 +298,7 @@ int sfc_sort(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out, uint64_t
     uint32_t *perm = nullptr;
     e = launch_radix_sort(ctx->stream, in->n, in->n_boxes, ctx->sb, keys_out, &perm);
     if (e != hipSuccess) return hip_fail(ctx, e, "radix sort");
-    e = launch_gather(ctx->stream, in, out, perm, perm_out);
+    e = launch_gather(ctx->stream, in, out, perm, ctx->sb.rec, perm_out);
     if (e != hipSuccess) return hip_fail(ctx, e, "gather");
     ctx->tree_leaf = 0;
     ctx->have_groups = 0;

@@ -58,9 +58,15 @@ struct GroupCfg {
     const sfc_group_params *gp_box;
 };
 
-// one wave per chunk
+// actives of a chunk whose positions sit in LDS at a time
+constexpr int GSTAGE = 512;
+
+// one wave per chunk; the greedy scan reads positions from LDS, staged
+// GSTAGE actives at a time with independent (coalesced-index) loads, so
+// that each group costs no global-memory round trip
 __global__ __launch_bounds__(64) void k_group_chunks(GroupCfg c)
 {
+    __shared__ double sx[GSTAGE], sy[GSTAGE], sz[GSTAGE], sh[GSTAGE];
     int64_t q = (int64_t)blockIdx.x;
     int lane = lane_id();
     int64_t nch = c.chunk_base[c.nb];
@@ -84,6 +90,7 @@ __global__ __launch_bounds__(64) void k_group_chunks(GroupCfg c)
     double L = c.box_L[b];
     int cap = gp.n_group_max;
     int64_t k = start;
+    int64_t t0 = 0, t1 = 0; // staged actives [t0, t1)
     int ng = 0;
     while (k < end) {
         if (lane == 0) c.gs_local[start + ng] = (int32_t)k;
@@ -93,16 +100,28 @@ __global__ __launch_bounds__(64) void k_group_chunks(GroupCfg c)
         if (gp.policy == SFC_POLICY_COUNT) {
             size = lim;
         } else {
-            int i0 = c.act[k];
-            double x0 = c.x[i0], y0 = c.y[i0], z0 = c.z[i0];
-            double R = gp.f * c.h[i0];
+            if (k + lim > t1) { // restage from k
+                t0 = k;
+                t1 = min(k + (int64_t)GSTAGE, end);
+                wave_lds_sync();
+                for (int j = lane; j < (int)(t1 - t0); j += 64) {
+                    const int i = c.act[t0 + j];
+                    sx[j] = c.x[i];
+                    sy[j] = c.y[i];
+                    sz[j] = c.z[i];
+                    sh[j] = c.h[i];
+                }
+                wave_lds_sync();
+            }
+            const int s0 = (int)(k - t0);
+            double x0 = sx[s0], y0 = sy[s0], z0 = sz[s0];
+            double R = gp.f * sh[s0];
             double R2 = R * R;
             bool pass = lane == 0;
             if (lane > 0 && lane < lim) {
-                int i = c.act[k + lane];
-                double dx = fold(c.x[i] - x0, L);
-                double dy = fold(c.y[i] - y0, L);
-                double dz = fold(c.z[i] - z0, L);
+                double dx = fold(sx[s0 + lane] - x0, L);
+                double dy = fold(sy[s0 + lane] - y0, L);
+                double dz = fold(sz[s0 + lane] - z0, L);
                 double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
                 pass = r2 < R2;
             }

@@ -180,7 +180,16 @@ __device__ __forceinline__ uint64_t mix64(uint64_t v)
 
 // ------------------------------------------------------- host-side launchers
 // (defined in the .hip files, called by the C-ABI layer)
+// a particle's fields in one 64-byte record (the gather's unit)
+struct __align__(64) PRec {
+    double x, y, z, h;
+    float m, vx, vy, vz, u, rho, fgrad;
+    uint32_t orig;
+};
+static_assert(sizeof(PRec) == 64, "PRec is one 64-byte record");
+
 struct SortBufs {
+    PRec *rec;               // [n] input-order records
     uint64_t *key_a, *key_b;
     uint32_t *val_a, *val_b;
     uint32_t *box_a, *box_b; // box ids (batched sort only)
@@ -192,7 +201,7 @@ hipError_t launch_keys(hipStream_t s, const sfc_particles *in, SortBufs &b);
 hipError_t launch_radix_sort(hipStream_t s, int64_t n, int nb, SortBufs &b, uint64_t *keys_out,
                              uint32_t **perm_out);
 hipError_t launch_gather(hipStream_t s, const sfc_particles *in, sfc_particles *out,
-                         const uint32_t *perm, uint32_t *perm_out);
+                         const uint32_t *perm, const PRec *rec, uint32_t *perm_out);
 size_t scan_tmp_elems(int64_t n);
 hipError_t launch_scan_excl_u32(hipStream_t s, const uint32_t *in, uint32_t *out, int64_t n,
                                 uint32_t *tmp, uint32_t *total);

@@ -61,27 +61,45 @@ __device__ __forceinline__ uint32_t key_cell(double x, double L)
     return (uint32_t)s;
 }
 
+// Keys, the sort payload (input index, with the active flag in bit 31: n <
+// 2^30) and the particle's 64-byte record: the fields are read here once, in
+// input order and coalesced, so that the gather after the sort fetches one
+// record per particle instead of one cache line per field.
 __global__ void k_keys(int64_t n, int nb, const int64_t *__restrict__ box_off,
-                       const double *__restrict__ box_L, const double *__restrict__ x,
-                       const double *__restrict__ y, const double *__restrict__ z,
+                       const double *__restrict__ box_L, const sfc_particles in,
                        uint64_t *__restrict__ key, uint32_t *__restrict__ val,
-                       uint32_t *__restrict__ boxid)
+                       uint32_t *__restrict__ boxid, PRec *__restrict__ rec)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int b = nb > 1 ? box_of(box_off, nb, i) : 0;
     double L = box_L[b];
-    key[i] = hilbert_key63(key_cell(x[i], L), key_cell(y[i], L), key_cell(z[i], L));
-    val[i] = (uint32_t)i;
+    const double x = in.x[i], y = in.y[i], z = in.z[i];
+    key[i] = hilbert_key63(key_cell(x, L), key_cell(y, L), key_cell(z, L));
+    val[i] = (uint32_t)i | (in.active[i] ? 0x80000000u : 0u);
     if (boxid) boxid[i] = (uint32_t)b;
+    PRec r;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.h = in.h[i];
+    r.m = in.m[i];
+    r.vx = in.vx ? in.vx[i] : 0.0f;
+    r.vy = in.vy ? in.vy[i] : 0.0f;
+    r.vz = in.vz ? in.vz[i] : 0.0f;
+    r.u = in.u ? in.u[i] : 0.0f;
+    r.rho = in.rho ? in.rho[i] : 0.0f;
+    r.fgrad = in.fgrad ? in.fgrad[i] : 0.0f;
+    r.orig = in.orig ? in.orig[i] : (uint32_t)i;
+    rec[i] = r;
 }
 
 hipError_t launch_keys(hipStream_t s, const sfc_particles *in, SortBufs &b)
 {
     int64_t n = in->n;
     int blocks = (int)((n + 255) / 256);
-    k_keys<<<blocks, 256, 0, s>>>(n, in->n_boxes, in->box_off, in->box_L, in->x, in->y, in->z,
-                                  b.key_a, b.val_a, in->n_boxes > 1 ? b.box_a : nullptr);
+    k_keys<<<blocks, 256, 0, s>>>(n, in->n_boxes, in->box_off, in->box_L, *in, b.key_a, b.val_a,
+                                  in->n_boxes > 1 ? b.box_a : nullptr, b.rec);
     return hipGetLastError();
 }
 
@@ -327,58 +345,42 @@ hipError_t launch_radix_sort(hipStream_t s, int64_t n, int nb, SortBufs &b, uint
 }
 
 // ------------------------------------------------------------------ gather
-struct GatherPtrs {
-    const void *src[16];
-    void *dst[16];
-    int size[16];
-    int count;
-};
-
-__global__ void k_gather(int64_t n, const uint32_t *__restrict__ perm, GatherPtrs g,
-                         const uint32_t *__restrict__ orig_in, uint32_t *__restrict__ orig_out,
-                         uint32_t *__restrict__ perm_out)
+// One record per output slot: the sorted order of every field, the active
+// flag from the payload's bit 31 (written as 0 / 1), the input index.
+__global__ void k_gather(int64_t n, const uint32_t *__restrict__ perm, const PRec *__restrict__ rec,
+                         sfc_particles out, uint32_t has, uint32_t *__restrict__ perm_out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t j = perm[i];
-    for (int f = 0; f < g.count; f++) {
-        if (g.size[f] == 8)
-            ((double *)g.dst[f])[i] = ((const double *)g.src[f])[j];
-        else if (g.size[f] == 4)
-            ((float *)g.dst[f])[i] = ((const float *)g.src[f])[j];
-        else
-            ((uint8_t *)g.dst[f])[i] = ((const uint8_t *)g.src[f])[j];
-    }
-    if (orig_out) orig_out[i] = orig_in ? orig_in[j] : j;
+    const uint32_t v = perm[i];
+    const uint32_t j = v & 0x7fffffffu;
+    const PRec r = rec[j];
+    out.x[i] = r.x;
+    out.y[i] = r.y;
+    out.z[i] = r.z;
+    out.h[i] = r.h;
+    out.m[i] = r.m;
+    if (has & 1u) out.vx[i] = r.vx;
+    if (has & 2u) out.vy[i] = r.vy;
+    if (has & 4u) out.vz[i] = r.vz;
+    if (has & 8u) out.u[i] = r.u;
+    if (has & 16u) out.rho[i] = r.rho;
+    if (has & 32u) out.fgrad[i] = r.fgrad;
+    if (has & 64u) out.orig[i] = r.orig;
+    out.active[i] = (uint8_t)(v >> 31);
     if (perm_out) perm_out[i] = j;
 }
 
 hipError_t launch_gather(hipStream_t s, const sfc_particles *in, sfc_particles *out,
-                         const uint32_t *perm, uint32_t *perm_out)
+                         const uint32_t *perm, const PRec *rec, uint32_t *perm_out)
 {
-    GatherPtrs g{};
-    auto add = [&](const void *a, void *b, int sz) {
-        if (a && b) {
-            g.src[g.count] = a;
-            g.dst[g.count] = b;
-            g.size[g.count] = sz;
-            g.count++;
-        }
-    };
-    add(in->x, out->x, 8);
-    add(in->y, out->y, 8);
-    add(in->z, out->z, 8);
-    add(in->h, out->h, 8);
-    add(in->m, out->m, 4);
-    add(in->vx, out->vx, 4);
-    add(in->vy, out->vy, 4);
-    add(in->vz, out->vz, 4);
-    add(in->u, out->u, 4);
-    add(in->rho, out->rho, 4);
-    add(in->fgrad, out->fgrad, 4);
-    add(in->active, out->active, 1);
+    // a field is written when both sides have it (x, y, z, h, m and active
+    // always do); orig is written whenever out has it
+    const uint32_t has = (in->vx && out->vx ? 1u : 0u) | (in->vy && out->vy ? 2u : 0u) |
+                         (in->vz && out->vz ? 4u : 0u) | (in->u && out->u ? 8u : 0u) |
+                         (in->rho && out->rho ? 16u : 0u) | (in->fgrad && out->fgrad ? 32u : 0u) |
+                         (out->orig ? 64u : 0u);
     int64_t n = in->n;
-    k_gather<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, perm, g, in->orig, out->orig,
-                                                          perm_out);
+    k_gather<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, perm, rec, *out, has, perm_out);
     return hipGetLastError();
 }

@@ -13,8 +13,8 @@
 // depth-first pre-order of the octree, so an exclusive scan of the counts
 // numbers the nodes, a node's first child is the next node and its skip link
 // is the first node starting at the end of its cell.  Bounding boxes and
-// max(h) are reduced from the leaves to the root with per-node arrival
-// counters (the last child to arrive combines the node).
+// max(h) are reduced from the leaves (one launch over all of them) to the
+// root, three levels per launch.
 #include "internal.h"
 
 __device__ __forceinline__ int common_levels(uint64_t a, uint64_t b)
@@ -42,7 +42,14 @@ __global__ void k_tree_count(int64_t n, int nb, const int64_t *__restrict__ box_
                              const int8_t *__restrict__ cwin, int8_t *__restrict__ dlev,
                              uint32_t *__restrict__ cnt)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the block's windows reach n_leaf entries back: stage them in LDS
+    extern __shared__ int8_t win[]; // [blockDim.x + n_leaf]
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t w0 = i0 - n_leaf > 0 ? i0 - n_leaf : 0;
+    const int64_t w1 = i0 + blockDim.x < n ? i0 + blockDim.x : n;
+    for (int64_t s = w0 + threadIdx.x; s < w1; s += blockDim.x) win[s - w0] = cwin[s];
+    __syncthreads();
+    int64_t i = i0 + threadIdx.x;
     if (i > n) return;
     if (i == n) {
         cnt[n] = 0;
@@ -52,7 +59,7 @@ __global__ void k_tree_count(int64_t n, int nb, const int64_t *__restrict__ box_
     int64_t bs = box_off[b];
     int64_t s0 = i - n_leaf > bs ? i - n_leaf : bs;
     int d = -1;
-    for (int64_t s = s0; s <= i; s++) d = max(d, (int)cwin[s]);
+    for (int64_t s = s0; s <= i; s++) d = max(d, (int)win[s - w0]);
     dlev[i] = (int8_t)d;
     int lo = lcp[i] + 1;
     int hi = min(SFC_KEY_BITS, d + 1);
@@ -173,63 +180,155 @@ __global__ void k_tree_nchild(const TreeDev t, const DevStatus *st)
 }
 
 
-// one level of the bottom-up pass: every node of `level` reduces its
-// particles (leaf) or its children (one level deeper, done by the previous
-// launch).  Levels go from the deepest to the root, one launch each, so no
-// node waits on another inside a kernel.
-__global__ void k_tree_level(const PartDev p, const TreeDev t, const DevStatus *st_in,
-                             DevStatus *st, int with_bbox, int level)
+// min / max over aligned groups of W lanes (W a power of two; the lanes of a
+// group are those that differ in the low log2(W) bits)
+template <int LO, int HI> __device__ __forceinline__ double xmin(double v)
+{
+#pragma unroll
+    for (int o = LO; o < HI; o <<= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <int LO, int HI> __device__ __forceinline__ double xmax(double v)
+{
+#pragma unroll
+    for (int o = LO; o < HI; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+struct NodeBox {
+    double lx, ly, lz, hx, hy, hz, hm;
+};
+__device__ __forceinline__ NodeBox box_empty()
+{
+    return NodeBox{INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+}
+__device__ __forceinline__ void box_add(NodeBox &b, const double4 &lo, const double4 &hi, bool bbox)
+{
+    b.hm = fmax(b.hm, lo.w);
+    if (bbox) {
+        b.lx = fmin(b.lx, lo.x); b.ly = fmin(b.ly, lo.y); b.lz = fmin(b.lz, lo.z);
+        b.hx = fmax(b.hx, hi.x); b.hy = fmax(b.hy, hi.y); b.hz = fmax(b.hz, hi.z);
+    }
+}
+template <int LO, int HI> __device__ __forceinline__ void box_reduce(NodeBox &b, bool bbox)
+{
+    b.hm = xmax<LO, HI>(b.hm);
+    if (bbox) {
+        b.lx = xmin<LO, HI>(b.lx); b.ly = xmin<LO, HI>(b.ly); b.lz = xmin<LO, HI>(b.lz);
+        b.hx = xmax<LO, HI>(b.hx); b.hy = xmax<LO, HI>(b.hy); b.hz = xmax<LO, HI>(b.hz);
+    }
+}
+__device__ __forceinline__ void box_store(const TreeDev &t, int id, const NodeBox &b, bool bbox)
+{
+    if (bbox) {
+        t.lo[id] = make_double4(b.lx, b.ly, b.lz, b.hm);
+        t.hi[id] = make_double4(b.hx, b.hy, b.hz, 0.0);
+    } else {
+        t.lo[id].w = b.hm;
+    }
+}
+
+// Leaves: every wave takes 64 node ids at a time; their leaves are reduced
+// over their particles eight at a time, each by a group of eight lanes that
+// strides through the particle range.
+__global__ void k_tree_leaves(const PartDev p, const TreeDev t, const DevStatus *st_in,
+                              DevStatus *st, int with_bbox)
 {
     const int nn = min(st_in->n_nodes, t.capacity);
-    const int stride = gridDim.x * blockDim.x;
-    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < nn; id += stride) {
-        const int4 inf = t.info[id];
-        if ((inf.w & 255) != level) continue;
-        double4 lo = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-        double4 hi = make_double4(-INFINITY, -INFINITY, -INFINITY, 0.0);
-        double hm = 0.0;
-        if (inf.w >> 8) {
-            int bad = 0;
-            const int b = p.nb > 1 ? box_of(p.box_off, p.nb, inf.x) : 0;
+    const int lane = lane_id();
+    const int grp = lane >> 3, sub = lane & 7;
+    const bool bbox = with_bbox != 0;
+    const int nw = (int)(gridDim.x * blockDim.x) >> 6;
+    for (int base = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < nn;
+         base += nw * 64) {
+        const int id = base + lane;
+        const int4 inf = id < nn ? t.info[id] : make_int4(0, 0, 0, 0);
+        uint64_t m = ballot(id < nn && (inf.w >> 8));
+        while (m) {
+            // the next (up to) eight leaves, one per lane group
+            int mine = -1;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int s = ctz64(m);
+                if (m) m &= m - 1;
+                if (grp == q && s < 64) mine = s;
+            }
+            // both reads with every lane active: a cross-lane read from a lane
+            // that is switched off returns 0
+            const int src = mine < 0 ? 0 : mine;
+            const int first = __shfl(inf.x, src, 64);
+            const int cnt_s = __shfl(inf.y, src, 64);
+            const int cnt = mine < 0 ? 0 : cnt_s;
+            const int b = p.nb > 1 && mine >= 0 ? box_of(p.box_off, p.nb, first) : 0;
             const double L = p.box_L[b];
-            const int i1 = inf.x + inf.y;
-#pragma unroll 4
-            for (int i = inf.x; i < i1; i++) {
-                double hh = p.h[i];
-                hm = fmax(hm, hh);
+            NodeBox bx = box_empty();
+            bool bad = false;
+            for (int i = first + sub; i < first + cnt; i += 8) {
+                const double hh = p.h[i];
+                bx.hm = fmax(bx.hm, hh);
                 bad |= !(hh > 0.0);
-                if (with_bbox) {
-                    double x = p.x[i], y = p.y[i], z = p.z[i];
-                    lo.x = fmin(lo.x, x); hi.x = fmax(hi.x, x);
-                    lo.y = fmin(lo.y, y); hi.y = fmax(hi.y, y);
-                    lo.z = fmin(lo.z, z); hi.z = fmax(hi.z, z);
+                if (bbox) {
+                    const double x = p.x[i], y = p.y[i], z = p.z[i];
+                    bx.lx = fmin(bx.lx, x); bx.hx = fmax(bx.hx, x);
+                    bx.ly = fmin(bx.ly, y); bx.hy = fmax(bx.hy, y);
+                    bx.lz = fmin(bx.lz, z); bx.hz = fmax(bx.hz, z);
                     bad |= !(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L);
                 }
             }
-            if (bad) atomicOr(&st->flags, SFC_ST_BAD_INPUT);
-        } else {
-            const int4 *kp = (const int4 *)(t.kids + 8 * (int64_t)id);
-            const int4 ka = kp[0], kb = kp[1];
-            const int kid[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+            if (ballot(bad) != 0ull && lane == 0) atomicOr(&st->flags, SFC_ST_BAD_INPUT);
+            box_reduce<1, 8>(bx, bbox);
+            if (sub == 0 && mine >= 0) box_store(t, base + mine, bx, bbox);
+        }
+    }
+}
+
+// Internal nodes of `level` together with their children and grandchildren:
+// one wave per node, lane 8c + g holding grandchild g of child c.  A
+// grandchild that is internal reduces its own children (level + 3: leaves, or
+// done by the launch before), a child reduces its eight lanes, the node its
+// eight children.  Launches go from level 18 up to 0 in steps of three.
+__global__ void k_tree_up3(const TreeDev t, const DevStatus *st_in, int with_bbox, int level)
+{
+    const int nn = min(st_in->n_nodes, t.capacity);
+    const int lane = lane_id();
+    const bool bbox = with_bbox != 0;
+    const int c = lane >> 3, g = lane & 7;
+    const int nw = (int)(gridDim.x * blockDim.x) >> 6;
+    for (int base = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < nn;
+         base += nw * 64) {
+        const int id = base + lane;
+        const int4 inf = id < nn ? t.info[id] : make_int4(0, 0, 0, 0);
+        uint64_t m = ballot(id < nn && !(inf.w >> 8) && (inf.w & 255) == level);
+        while (m) {
+            const int s = ctz64(m);
+            m &= m - 1;
+            const int nd = base + s;
+            const int ch = t.kids[8 * (int64_t)nd + c];
+            const bool ch_ok = ch >= 0 && ch < nn;
+            const bool ch_leaf = ch_ok && (t.info[ch].w >> 8);
+            NodeBox bx = box_empty();
+            if (ch_ok && ch_leaf) {
+                if (g == 0) box_add(bx, t.lo[ch], t.hi[ch], bbox);
+            } else if (ch_ok) {
+                const int gc = t.kids[8 * (int64_t)ch + g];
+                if (gc >= 0 && gc < nn) {
+                    if (t.info[gc].w >> 8) {
+                        box_add(bx, t.lo[gc], t.hi[gc], bbox);
+                    } else {
+                        const int4 *kp = (const int4 *)(t.kids + 8 * (int64_t)gc);
+                        const int4 ka = kp[0], kb = kp[1];
+                        const int kid[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
 #pragma unroll
-            for (int s = 0; s < 8; s++) {
-                const int c = kid[s];
-                if (c < 0 || c >= nn) continue;
-                const double4 clo = t.lo[c];
-                hm = fmax(hm, clo.w);
-                if (with_bbox) {
-                    const double4 chi = t.hi[c];
-                    lo.x = fmin(lo.x, clo.x); lo.y = fmin(lo.y, clo.y); lo.z = fmin(lo.z, clo.z);
-                    hi.x = fmax(hi.x, chi.x); hi.y = fmax(hi.y, chi.y); hi.z = fmax(hi.z, chi.z);
+                        for (int k = 0; k < 8; k++)
+                            if (kid[k] >= 0 && kid[k] < nn) box_add(bx, t.lo[kid[k]], t.hi[kid[k]], bbox);
+                        box_store(t, gc, bx, bbox);
+                    }
                 }
             }
-        }
-        if (with_bbox) {
-            lo.w = hm;
-            t.lo[id] = lo;
-            t.hi[id] = hi;
-        } else {
-            t.lo[id].w = hm;
+            box_reduce<1, 8>(bx, bbox); // the child
+            if (ch_ok && !ch_leaf && g == 0) box_store(t, ch, bx, bbox);
+            box_reduce<8, 64>(bx, bbox); // the node
+            if (lane == 0) box_store(t, nd, bx, bbox);
         }
     }
 }
@@ -243,8 +342,8 @@ hipError_t launch_tree_build(hipStream_t s, const PartDev &p, const uint64_t *ke
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // cwin lives in the (not yet used) start buffer
-    k_tree_count<<<gb, 256, 0, s>>>(n, p.nb, p.box_off, n_leaf, tb.lcp, (const int8_t *)tb.start,
-                                    tb.dlev, tb.cnt);
+    k_tree_count<<<gb, 256, 256 + n_leaf, s>>>(n, p.nb, p.box_off, n_leaf, tb.lcp,
+                                               (const int8_t *)tb.start, tb.dlev, tb.cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     e = launch_scan_excl_u32(s, tb.cnt, tb.start, n + 1, scan_tmp, nullptr);
     if (e != hipSuccess) return e;
@@ -262,14 +361,17 @@ hipError_t launch_tree_refit(hipStream_t s, const PartDev &p, TreeDev &t, bool b
     (void)n;
     // grid-stride kernels over the nodes (their number is known on the device only)
     int64_t g = (t.capacity + 255) / 256;
-    const unsigned gnodes = (unsigned)(g < 2048 ? g : 2048);
+    const unsigned gnodes = (unsigned)(g < 1024 ? g : 1024);
     hipError_t e;
     if (bbox) { // a new tree: child counts and the child table
         k_tree_nchild<<<gnodes, 256, 0, s>>>(t, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    for (int level = SFC_KEY_BITS; level >= 0; level--) {
-        k_tree_level<<<gnodes, 256, 0, s>>>(p, t, st, st, bbox ? 1 : 0, level);
+    k_tree_leaves<<<gnodes, 256, 0, s>>>(p, t, st, st, bbox ? 1 : 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // level 21 holds leaves only; levels 20 .. 0 in three-level steps
+    for (int level = SFC_KEY_BITS - 3; level >= 0; level -= 3) {
+        k_tree_up3<<<gnodes, 256, 0, s>>>(t, st, bbox ? 1 : 0, level);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

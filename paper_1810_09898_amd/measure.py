@@ -9,7 +9,9 @@ density + hydro, and the status counters of one step.
 - plummer_batch: the 64-box batch in one launch per phase, with a per-box
   group parameter table (dense boxes: cap 32, sparse ones: cap 8).
 - lognormal_bins: three nested timestep bins (all, 10 %, 1 % active) of the
-  large lognormal box; one line per bin.
+  large lognormal box; one line per bin, each with the step also captured in
+  a HIP graph and replayed, and the FP32-compensated results compared with
+  the FP64-accumulator variant on the GPU (relative errors per field).
 - the other workloads: one line.
 """
 from __future__ import annotations
@@ -24,28 +26,85 @@ import numpy as np
 
 def _phases(pl, reps):
     import torch
+    torch.cuda.synchronize()
     names = ["sort", "tree", "groups", "density", "hydro"]
     calls = [pl.sort, pl.tree, pl.groups, pl.density, pl.hydro_force if pl.hydro else None]
     out = {k: [] for k in names}
+    st = pl.ctx.stream
     for _ in range(reps):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in names]
         for (a, b), f in zip(ev, calls):
-            a.record()
+            a.record(st)
             if f is not None:
                 f()
-            b.record()
+            b.record(st)
         torch.cuda.synchronize()
         for k, (a, b) in zip(names, ev):
             out[k].append(a.elapsed_time(b))
     return {k: float(np.median(v)) for k, v in out.items()}
 
 
-def run(w, cfg, label, steps, gp_box=None):
+def _graph_ms(pl, reps):
+    """the whole step captured once as a HIP graph, median of `reps` replays"""
+    import torch
+    s = pl.ctx.stream
+    pl.ctx.graph_begin()
+    pl.step()
+    g = pl.ctx.graph_end()
+    out = []
+    try:
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            pl.ctx.graph_launch(g)
+            b.record(s)
+            s.synchronize()
+            out.append(a.elapsed_time(b))
+    finally:
+        pl.ctx.graph_destroy(g)
+    return float(np.median(out))
+
+
+def _precision(w, cfg, pl32):
+    """FP32-compensated sums of `pl32` against the FP64-accumulator variant
+    of the same step (same neighbour sets and h): per field, the largest and
+    the 99.9th percentile relative error over the active particles (vectors:
+    |a32 - a64| / |a64|; du/dt: |du32 - du64| / rms du64)."""
+    import torch
+    from . import sfcngb as S
+    from .pipeline import Pipeline
+    r32 = {**pl32.sorted_numpy(("h", "rho", "active")), **pl32.outputs_numpy()}
+    pl = Pipeline(w, cfg.with_(accum=S.ACCUM_F64), hydro=pl32.hydro)
+    pl.step()
+    torch.cuda.synchronize()
+    r64 = {**pl.sorted_numpy(("h", "active")), **pl.outputs_numpy()}
+    del pl
+    act = r32["active"] != 0
+    out = {"same_h": bool(np.array_equal(r32["h"], r64["h"]))}
+
+    def stats(e):
+        e = e[act]
+        return {"max": float(e.max()), "p999": float(np.quantile(e, 0.999))}
+
+    with np.errstate(divide="ignore", invalid="ignore"):  # inactive particles hold zeros
+        out["rho"] = stats(np.abs(r32["rho"].astype(np.float64) / r64["rho64"] - 1.0))
+        if pl32.hydro:
+            a32 = np.stack([r32[k].astype(np.float64) for k in ("ax", "ay", "az")])
+            a64 = np.stack([r64[k + "64"] for k in ("ax", "ay", "az")])
+            out["acc"] = stats(np.linalg.norm(a32 - a64, axis=0) / np.linalg.norm(a64, axis=0))
+            du = r64["dudt64"]
+            out["dudt"] = stats(np.abs(r32["dudt"] - du) / np.sqrt(np.mean(du[act] ** 2)))
+    return out
+
+
+def run(w, cfg, label, steps, gp_box=None, graph=False, precision=False):
     import torch
     from .pipeline import Pipeline
     gpb = None if gp_box is None else torch.as_tensor(gp_box, device="cuda")
-    pl = Pipeline(w, cfg, gp_box=gpb)
+    side = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+    with torch.cuda.stream(side):
+        pl = Pipeline(w, cfg, gp_box=gpb)
     pl.step()
     torch.cuda.synchronize()
     pl.ctx.status_clear()
@@ -60,9 +119,21 @@ def run(w, cfg, label, steps, gp_box=None):
             "density_plus_hydro_updates_per_s": round(A / ((ph["density"] + ph["hydro"]) * 1e-3), 1),
             "status": st, "config": {k: getattr(cfg, k) for k in
                                      ("n_leaf", "policy", "n_group_max", "f", "t_cand", "skin")}}
+    if graph:
+        line["graph_step_ms"] = round(_graph_ms(pl, steps), 4)
+    if precision:
+        line["fp32_vs_fp64"] = _precision(w, cfg, pl)
     print(json.dumps(line), flush=True)
     del pl
     return line
+
+
+def _bin_configs():
+    from .pipeline import StepConfig
+    # chosen by autotune.py (`--workload lognormal_bins --bins 0,1,2`)
+    return {0: StepConfig(n_leaf=64, n_group_max=36, f=0.4, t_cand=2048, hydro_t_cand=2048),
+            1: StepConfig(n_leaf=64, n_group_max=36, f=0.5, t_cand=2048, hydro_t_cand=2048),
+            2: StepConfig(n_leaf=64, n_group_max=36, f=0.5, t_cand=2048, hydro_t_cand=2048)}
 
 
 def main():
@@ -74,6 +145,8 @@ def main():
     from . import autotune
     from .pipeline import StepConfig
     W.VERBOSE = True
+    global BIN_CONFIGS
+    BIN_CONFIGS = _bin_configs()
     t0 = time.time()
     w = W.WORKLOADS[args.workload]()
     print(f"# {args.workload}: generated in {time.time() - t0:.1f} s, n={w.n}", file=sys.stderr,
@@ -83,12 +156,12 @@ def main():
         run(w, cfg, "plummer_batch (per-box parameters)", args.steps,
             gp_box=autotune.per_box_params(w, autotune.batch_rule))
     elif args.workload == "lognormal_bins":
-        cfg = StepConfig(n_leaf=32, n_group_max=36, f=0.6, t_cand=2048, hydro_t_cand=2048)
         base = dict(w.state)
         for b, frac in ((0, "100%"), (1, "10%"), (2, "1%")):
             w.state = dict(base)
             w.state["active"] = (base["bin"] >= b).astype(np.uint8)
-            run(w, cfg, f"lognormal_bins bin {b} ({frac} active)", args.steps)
+            run(w, BIN_CONFIGS[b], f"lognormal_bins bin {b} ({frac} active)", args.steps,
+                graph=True, precision=True)
     else:
         cfg = StepConfig(n_leaf=32, n_group_max=36, f=0.6, t_cand=2048, hydro_t_cand=2048)
         if w.n_ngb < 100:

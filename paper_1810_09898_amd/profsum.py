@@ -6,7 +6,7 @@
     python -m paper_1810_09898_amd.profsum pmc OUT.json --cmd "..." \\
         --calib-fetch DIR --calib-write DIR RUN_DIR [RUN_DIR ...]
         per-call counter totals from `rocprofv3 --pmc ... --output-format csv`
-        runs of bench.py.  FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are
+        runs of bench.py, as JSON and as a text table (OUT with .txt).  FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are
         scaled by the reading of a plain copy of known size (calib.py) to give
         HBM bytes.  A "call" is one library entry point: density = the walk
         and the per-particle kernel; hydro_force = the max-h refit, the record
@@ -87,7 +87,7 @@ def _calls(disp):
             seg = [items[k]]
             j = k - 1
             while j >= 0 and items[j][1][0] in ("k_walk", "k_reset_pass", "k_hydro_prep",
-                                                 "k_tree_level", "k_tree_nchild"):
+                                                 "k_tree_leaves", "k_tree_up3", "k_tree_nchild"):
                 seg.insert(0, items[j])
                 j -= 1
             calls["hydro_force"].append(seg)
@@ -127,10 +127,37 @@ def pmc(out: str, cmd: str, calib_fetch: str, calib_write: str, runs) -> dict:
             e["valu_insts"] = m["SQ_INSTS_VALU"]
         res["calls"][call] = e
     for k, cs in per_kernel.items():
-        res["kernels"][k] = {c: sum(v) / len(v) for c, v in sorted(cs.items())}
+        m = {c: sum(v) / len(v) for c, v in sorted(cs.items())}
+        if "FETCH_SIZE" in m and "WRITE_SIZE" in m:
+            m["hbm_bytes"] = m["FETCH_SIZE"] * 1024 * f_fetch + m["WRITE_SIZE"] * 1024 * f_write
+        res["kernels"][k] = m
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1)
+    with open(os.path.splitext(out)[0] + ".txt", "w") as fh:
+        fh.write(_table(res))
     return res
+
+
+def _table(res) -> str:
+    cols = (("hbm_bytes", "HBM GB", 1e9), ("SQ_INSTS_VALU", "VALU M", 1e6),
+            ("SQ_INSTS_SALU", "SALU M", 1e6), ("SQ_INSTS_LDS", "LDS M", 1e6),
+            ("SQ_INSTS_VMEM_RD", "VMEM M", 1e6))
+    lines = ["# PMC counters per call and per kernel, 2M lognormal step (benchmark configuration)",
+             f"# {res['command']}",
+             f"# copy-kernel calibration: FETCH_SIZE x {res['copy_factor_fetch']:.4f}, "
+             f"WRITE_SIZE x {res['copy_factor_write']:.4f} -> bytes",
+             "# values are per dispatch (per call for the calls), averaged over the dispatches "
+             "of the runs", "",
+             f"{'call/kernel':30s} " + " ".join(f"{h:>9s}" for _, h, _ in cols)]
+    rows = [(f"call {k}", v) for k, v in res["calls"].items()]
+    rows += sorted(res["kernels"].items(), key=lambda kv: -kv[1].get("hbm_bytes", 0.0))
+    for name, v in rows:
+        if v.get("hbm_bytes", 0.0) < 1e7 and not name.startswith("call"):
+            continue
+        lines.append(f"{name[:30]:30s} " + " ".join(f"{v.get(c, 0.0) / sc:9.3f}" if c == "hbm_bytes"
+                                                  else f"{v.get(c, 0.0) / sc:9.1f}"
+                                                  for c, _, sc in cols))
+    return "\n".join(lines) + "\n"
 
 
 def main():

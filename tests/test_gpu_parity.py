@@ -101,7 +101,7 @@ def _tree_arrays(pl):
 
 
 @pytest.mark.parametrize("name,n_leaf", [("plum_small", 8), ("plum_small", 16), ("plum_small", 64),
-                                         ("uni", 32), ("batch", 16)])
+                                         ("plum_small", 256), ("uni", 32), ("batch", 16)])
 def test_octree_matches_oracle(name, n_leaf, request):
     w = request.getfixturevalue(name)
     say(f"[tree] {name} n_leaf={n_leaf}")
@@ -395,9 +395,26 @@ def test_hydro_fallback_bits(logn):
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
-def test_step_end_to_end(logn):
+def test_results_independent_of_leaf_size(plum):
+    """The leaf size changes the walks and the supersets, not the neighbour
+    lists nor their order: every result is bit-identical."""
+    say("[leaf] n_leaf 8 / 64 / 256")
+    outs = []
+    for n_leaf in (8, 64, 256):
+        pl = Pipeline(plum, StepConfig(n_leaf=n_leaf, n_group_max=16, f=0.5, t_cand=1024))
+        pl.step()
+        _sync()
+        assert pl.ctx.status()["flags"] == 0
+        outs.append({**pl.sorted_numpy(("h", "rho", "fgrad")), **pl.outputs_numpy()})
+    for o in outs[1:]:
+        for k in ("h", "rho", "fgrad", "drhodh", "nngb", "iters"):
+            assert np.array_equal(outs[0][k], o[k]), k
+
+
+@pytest.mark.parametrize("n_leaf", [16, 128])
+def test_step_end_to_end(logn, n_leaf):
     """Density (h loop) then hydro: each side uses its own density."""
-    say("[step] lognormal density + hydro")
+    say(f"[step] lognormal density + hydro, n_leaf={n_leaf}")
     ob, keys, perm, s, act = osorted(logn)
     r = oracle.density(s["x"], s["y"], s["z"], s["h"], s["m"], ob, act, 1, 295, 6, use_grid=True)
     h = s["h"].copy()
@@ -406,7 +423,8 @@ def test_step_end_to_end(logn):
     h[act], rho[act], fg[act] = r.h, r.rho, r.fgrad
     hr = oracle.hydro(s["x"], s["y"], s["z"], h, s["m"], s["vx"], s["vy"], s["vz"], s["u"], rho,
                       fg, ob, act, 1, use_grid=True)
-    pl = Pipeline(logn, StepConfig(n_group_max=32, t_cand=2048, hydro_t_cand=2048))
+    pl = Pipeline(logn, StepConfig(n_leaf=n_leaf, n_group_max=32, t_cand=2048,
+                                   hydro_t_cand=2048))
     pl.step()
     _sync()
     assert pl.ctx.status()["flags"] == 0
