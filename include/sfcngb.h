@@ -133,13 +133,20 @@ SFC_API int tree_refit_hmax(sfc_ctx *ctx, const sfc_particles *p);
 /* ---------------------------------------------------------------------- */
 #define SFC_POLICY_COUNT 0 /* n_group_max consecutive actives */
 #define SFC_POLICY_PAPER 1 /* greedy radius rule, R = f h_0 */
+#define SFC_POLICY_TREE 2  /* the actives of one octree node of depth `level` */
 
 typedef struct {
-    int32_t policy;      /* SFC_POLICY_COUNT or SFC_POLICY_PAPER */
+    int32_t policy;      /* SFC_POLICY_COUNT, SFC_POLICY_PAPER or SFC_POLICY_TREE */
     int32_t n_group_max; /* 1..64 members per group */
     double f;            /* paper policy: a particle joins while closer than f*h_0 to the
                             group's first member (section "Adaptive Neighbour Recycling") */
     int32_t chunk;       /* the greedy scan restarts every `chunk` actives of a box (>= 64) */
+    int32_t level;       /* tree policy (0..21): a particle joins while it lies in the octree
+                            node of depth `level` that holds the group's first member, or, when
+                            that member's leaf is shallower, in that leaf (section "Neighbour
+                            Recycling": groups as the leaves inside nodes of one tree depth).
+                            Node = Hilbert cell of the last tree_build, so the tree and its
+                            n_leaf decide the leaves. */
 } sfc_group_params;
 
 /* Optional neighbour-set dump (testing): for every active particle i,

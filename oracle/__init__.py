@@ -66,7 +66,8 @@ def _declare(L):
     L.orc_octree.argtypes = [_I64, _P, _I32, _P, _I32, _I32, _P, _P, _P, _P, _I64,
                              _P, _P, _P, _P, _P, _P, _P]
     L.orc_groups.restype = _I64
-    L.orc_groups.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P]
+    L.orc_groups.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _I32,
+                             _P]
     L.orc_ngb_count.restype = None
     L.orc_ngb_count.argtypes = [_I32, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _I64, _P,
                                 _I32, _P, _P]
@@ -196,6 +197,7 @@ def octree(keys_sorted, x, y, z, h, boxes: Boxes, n_leaf: int,
 # --------------------------------------------------------------------------
 POLICY_COUNT = 0
 POLICY_PAPER = 1
+POLICY_TREE = 2
 
 
 def _per_box(v, nbox, dtype):
@@ -205,9 +207,19 @@ def _per_box(v, nbox, dtype):
     return _c(a, dtype)
 
 
-def groups(act, x, y, z, h, boxes: Boxes, policy, n_group_max, f, chunk: int) -> np.ndarray:
+def leaf_levels(tree: Tree, n: int) -> np.ndarray:
+    """Depth of the leaf that holds each particle."""
+    out = np.full(n, -1, np.int32)
+    for k in np.nonzero(tree.leaf)[0]:
+        out[tree.first[k]:tree.first[k] + tree.count[k]] = tree.level[k]
+    return out
+
+
+def groups(act, x, y, z, h, boxes: Boxes, policy, n_group_max, f, chunk: int, level=0,
+           leaf_level=None) -> np.ndarray:
     """Group starts (positions in `act`, plus A at the end) of the greedy
-    grouping along the curve; policy/n_group_max/f scalar or per box."""
+    grouping along the curve; policy/n_group_max/f/level scalar or per box.
+    The tree policy needs leaf_level (leaf_levels() of the octree)."""
     act = _c(act, np.int32)
     x, y, z, h = (_c(a, np.float64) for a in (x, y, z, h))
     box = _c(boxes.box_of(), np.int32)
@@ -215,10 +227,14 @@ def groups(act, x, y, z, h, boxes: Boxes, policy, n_group_max, f, chunk: int) ->
     pol = _per_box(policy, nb, np.int32)
     cap = _per_box(n_group_max, nb, np.int32)
     ff = _per_box(f, nb, np.float64)
+    lev = _per_box(level, nb, np.int32)
+    if np.any(pol == POLICY_TREE) and leaf_level is None:
+        raise ValueError("the tree policy needs leaf_level")
+    ll = _c(leaf_level if leaf_level is not None else np.zeros(len(x)), np.int32)
     out = np.empty(len(act) + 1, np.int32)
     G = _lib().orc_groups(len(act), _ptr(act), _ptr(x), _ptr(y), _ptr(z), _ptr(h),
                           _ptr(box), _ptr(_c(boxes.L, np.float64)), _ptr(pol), _ptr(cap),
-                          _ptr(ff), chunk, _ptr(out))
+                          _ptr(ff), chunk, _ptr(lev), _ptr(ll), KEY_BITS, _ptr(out))
     return out[:G + 1].copy()
 
 

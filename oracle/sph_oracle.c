@@ -212,12 +212,21 @@ int64_t orc_octree(int64_t n, const uint64_t *key, int32_t nbox, const int64_t *
 /* box, never exceeds n_group_max members, and the scan restarts every */
 /* `chunk` actives of a box (each worker walks its own slice of the    */
 /* active list).  policy 0 ("count") drops the distance test.          */
+/* policy 2 ("tree", section "Adaptive Neighbour Recycling": a group   */
+/* is the set of leaves inside a node of one tree depth): a particle   */
+/* joins while it lies in the same octree node as the group's first    */
+/* particle, the node being that particle's ancestor of depth          */
+/* level[b], or its leaf when the leaf is shallower (leaf_level[i] =   */
+/* depth of the leaf holding particle i).  Nodes are cubes of the      */
+/* 2^l grid, so "same node of depth l" = same cell index >> (bits-l)  */
+/* on every axis.                                                      */
 /* gstart[0..G] receives group starts (positions in act), gstart[G]=A. */
 /* ------------------------------------------------------------------ */
 int64_t orc_groups(int64_t A, const int32_t *act, const double *x, const double *y,
                    const double *z, const double *h, const int32_t *box,
                    const double *box_L, const int32_t *policy, const int32_t *n_group_max,
-                   const double *f, int64_t chunk, int32_t *gstart)
+                   const double *f, int64_t chunk, const int32_t *level,
+                   const int32_t *leaf_level, int32_t bits, int32_t *gstart)
 {
     int64_t G = 0;
     int64_t k0 = -1, size = 0, box_first = 0;
@@ -243,6 +252,14 @@ int64_t orc_groups(int64_t A, const int32_t *act, const double *x, const double 
                 double r2 = orc_r2(x[i0], y[i0], z[i0], x[i], y[i], z[i], L);
                 double R = f[b] * h[i0];
                 if (!(r2 < R * R))
+                    open = 1;
+            } else if (policy[b] == 2) {
+                double L = box_L[b];
+                int32_t d = level[b] < leaf_level[i0] ? level[b] : leaf_level[i0];
+                int32_t sh = bits - d;
+                if ((orc_cell(x[i], L, bits) >> sh) != (orc_cell(x[i0], L, bits) >> sh) ||
+                    (orc_cell(y[i], L, bits) >> sh) != (orc_cell(y[i0], L, bits) >> sh) ||
+                    (orc_cell(z[i], L, bits) >> sh) != (orc_cell(z[i0], L, bits) >> sh))
                     open = 1;
             }
         }

@@ -32,6 +32,7 @@ NG_GRID = (4, 8, 16, 24, 32, 48, 64)
 T_GRID = (1024, 2048, 4096)
 LEAF_GRID = (8, 16, 32, 64, 128, 256)
 SKIN_GRID = (1.0, 1.05, 1.1)
+LEVEL_GRID = (3, 4, 5, 6, 7, 8)  # tree policy: depth of the grouping nodes
 
 CACHE = os.environ.get("SFCNGB_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib",
@@ -86,7 +87,8 @@ def measure(w, cfg: StepConfig, reps: int = 3) -> dict:
 
 
 def _key(cfg):
-    return (cfg.policy, cfg.n_group_max, round(cfg.f, 3), cfg.t_cand, cfg.n_leaf, cfg.skin)
+    return (cfg.policy, cfg.n_group_max, round(cfg.f, 3), cfg.t_cand, cfg.n_leaf, cfg.skin,
+            cfg.level if cfg.policy == S.POLICY_TREE else -1)
 
 
 def tune(w, base: StepConfig | None = None, rounds: int = 2, log=print, objective="step_ms"):
@@ -109,7 +111,8 @@ def tune(w, base: StepConfig | None = None, rounds: int = 2, log=print, objectiv
         improved = False
         axes = [
             [best.with_(policy=S.POLICY_PAPER, f=f) for f in F_GRID]
-            + [best.with_(policy=S.POLICY_COUNT, f=0.0)],
+            + [best.with_(policy=S.POLICY_COUNT, f=0.0)]
+            + [best.with_(policy=S.POLICY_TREE, level=lv) for lv in LEVEL_GRID],
             [best.with_(n_group_max=g) for g in NG_GRID],
             [best.with_(t_cand=t, hydro_t_cand=t) for t in T_GRID],
             [best.with_(n_leaf=l) for l in LEAF_GRID],
@@ -148,14 +151,15 @@ def tuned_config(w, retune=False, log=print) -> StepConfig:
 
 def per_box_params(w, cfg_for_box) -> np.ndarray:
     """Per-box group parameter table (device layout of sfc_group_params) for a
-    batch of boxes: cfg_for_box(b, n_b, active_fraction) -> (policy, cap, f, chunk)."""
+    batch of boxes: cfg_for_box(b, n_b, active_fraction) -> (policy, cap, f, chunk[,
+    level])."""
     nb = len(w.box_L)
     arr = (S.GroupParams * nb)()
     for b in range(nb):
         a0, a1 = int(w.box_off[b]), int(w.box_off[b + 1])
         frac = float(w.state["active"][a0:a1].mean()) if a1 > a0 else 0.0
-        pol, cap, f, chunk = cfg_for_box(b, a1 - a0, frac)
-        arr[b] = S.GroupParams(int(pol), int(cap), float(f), int(chunk))
+        pol, cap, f, chunk, *lev = cfg_for_box(b, a1 - a0, frac)
+        arr[b] = S.GroupParams(int(pol), int(cap), float(f), int(chunk), int(lev[0]) if lev else 0)
     return np.frombuffer(bytes(arr), dtype=np.uint8).copy()
 
 

@@ -336,8 +336,11 @@ int tree_refit_hmax(sfc_ctx *ctx, const sfc_particles *p)
 
 static int check_group_params(sfc_ctx *ctx, const sfc_group_params *gp)
 {
-    if (gp->policy != SFC_POLICY_COUNT && gp->policy != SFC_POLICY_PAPER)
+    if (gp->policy != SFC_POLICY_COUNT && gp->policy != SFC_POLICY_PAPER &&
+        gp->policy != SFC_POLICY_TREE)
         return fail(ctx, SFC_EINVAL, "group params: bad policy %d", gp->policy);
+    if (gp->policy == SFC_POLICY_TREE && (gp->level < 0 || gp->level > SFC_KEY_BITS))
+        return fail(ctx, SFC_EINVAL, "group params: level %d outside [0, 21]", gp->level);
     if (gp->n_group_max < 1 || gp->n_group_max > SFC_WAVE_GROUP_MAX)
         return fail(ctx, SFC_EINVAL, "group params: n_group_max %d outside [1, 64]", gp->n_group_max);
     if (gp->policy == SFC_POLICY_PAPER && !(gp->f >= 0.0))
@@ -372,8 +375,8 @@ int group_ngb_search(sfc_ctx *ctx, const sfc_particles *p, const sfc_group_param
             return fail(ctx, SFC_EINVAL, "verify: list needs list_off");
     }
     PartDev pd = part_dev(p);
-    hipError_t e = launch_groups(ctx->stream, pd, gp_box ? nullptr : gp, gp_box, ctx->gb,
-                                 ctx->scan_tmp, ctx->st);
+    hipError_t e = launch_groups(ctx->stream, pd, gp_box ? nullptr : gp, gp_box, ctx->tb.dlev,
+                                 ctx->gb, ctx->scan_tmp, ctx->st);
     if (e != hipSuccess) return hip_fail(ctx, e, "groups");
     ctx->have_groups = 1;
     if (verify) {

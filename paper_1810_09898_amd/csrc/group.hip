@@ -56,6 +56,8 @@ struct GroupCfg {
     int64_t max_chunks;
     sfc_group_params gp;          // used when gp_box == NULL
     const sfc_group_params *gp_box;
+    const int8_t *dlev; // per particle: deepest level whose cell holds more than n_leaf
+                        // particles (-1: none), so its leaf lies at min(21, dlev + 1)
 };
 
 // actives of a chunk whose positions sit in LDS at a time
@@ -67,6 +69,7 @@ constexpr int GSTAGE = 512;
 __global__ __launch_bounds__(64) void k_group_chunks(GroupCfg c)
 {
     __shared__ double sx[GSTAGE], sy[GSTAGE], sz[GSTAGE], sh[GSTAGE];
+    __shared__ int sl[GSTAGE]; // tree policy: leaf level of each staged active
     int64_t q = (int64_t)blockIdx.x;
     int lane = lane_id();
     int64_t nch = c.chunk_base[c.nb];
@@ -84,6 +87,7 @@ __global__ __launch_bounds__(64) void k_group_chunks(GroupCfg c)
     sfc_group_params gp = c.gp_box ? c.gp_box[b] : c.gp;
     gp.chunk = max(gp.chunk, 64); // per-box tables are device data: keep them in range
     gp.n_group_max = min(max(gp.n_group_max, 1), 64);
+    gp.level = min(max(gp.level, 0), SFC_KEY_BITS);
     int64_t a0 = c.fscan[c.box_off[b]], a1 = c.fscan[c.box_off[b + 1]];
     int64_t start = a0 + (q - (int64_t)c.chunk_base[b]) * gp.chunk;
     int64_t end = min(start + (int64_t)gp.chunk, a1);
@@ -110,20 +114,33 @@ __global__ __launch_bounds__(64) void k_group_chunks(GroupCfg c)
                     sy[j] = c.y[i];
                     sz[j] = c.z[i];
                     sh[j] = c.h[i];
+                    if (gp.policy == SFC_POLICY_TREE) sl[j] = min((int)c.dlev[i] + 1, SFC_KEY_BITS);
                 }
                 wave_lds_sync();
             }
             const int s0 = (int)(k - t0);
             double x0 = sx[s0], y0 = sy[s0], z0 = sz[s0];
-            double R = gp.f * sh[s0];
-            double R2 = R * R;
             bool pass = lane == 0;
-            if (lane > 0 && lane < lim) {
-                double dx = fold(sx[s0 + lane] - x0, L);
-                double dy = fold(sy[s0 + lane] - y0, L);
-                double dz = fold(sz[s0 + lane] - z0, L);
-                double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                pass = r2 < R2;
+            if (gp.policy == SFC_POLICY_TREE) {
+                // same cell as the first member at the depth of its node: the
+                // chosen level, or its leaf's when that is shallower
+                const int sh3 = SFC_KEY_BITS - min(gp.level, sl[s0]);
+                const uint32_t cx = key_cell(x0, L) >> sh3, cy = key_cell(y0, L) >> sh3,
+                               cz = key_cell(z0, L) >> sh3;
+                if (lane > 0 && lane < lim)
+                    pass = (key_cell(sx[s0 + lane], L) >> sh3) == cx &&
+                           (key_cell(sy[s0 + lane], L) >> sh3) == cy &&
+                           (key_cell(sz[s0 + lane], L) >> sh3) == cz;
+            } else {
+                double R = gp.f * sh[s0];
+                double R2 = R * R;
+                if (lane > 0 && lane < lim) {
+                    double dx = fold(sx[s0 + lane] - x0, L);
+                    double dy = fold(sy[s0 + lane] - y0, L);
+                    double dz = fold(sz[s0 + lane] - z0, L);
+                    double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                    pass = r2 < R2;
+                }
             }
             size = ctz64(~ballot(pass));
         }
@@ -164,8 +181,8 @@ __global__ __launch_bounds__(64) void k_group_scatter(GroupCfg c, const uint32_t
 }
 
 hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params *gp,
-                         const sfc_group_params *gp_box, GroupBufs &g, uint32_t *scan_tmp,
-                         DevStatus *st)
+                         const sfc_group_params *gp_box, const int8_t *dlev, GroupBufs &g,
+                         uint32_t *scan_tmp, DevStatus *st)
 {
     int64_t n = p.n;
     unsigned gb = (unsigned)((n + 1 + 255) / 256);
@@ -197,8 +214,9 @@ hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params
     c.gcount = g.gcount;
     c.max_chunks = g.max_chunks;
     if (gp) c.gp = *gp;
-    else c.gp = sfc_group_params{SFC_POLICY_COUNT, 1, 0.0, 64};
+    else c.gp = sfc_group_params{SFC_POLICY_COUNT, 1, 0.0, 64, 0};
     c.gp_box = gp_box;
+    c.dlev = dlev;
     k_group_chunks<<<(unsigned)g.max_chunks, 64, 0, s>>>(c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // gcount[max_chunks] = 0 so that the scan's last entry is the group total

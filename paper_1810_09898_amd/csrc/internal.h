@@ -10,6 +10,16 @@
 #define SFC_KEY_BITS 21
 #define SFC_WG 256 // threads per workgroup in the persistent kernels (4 waves)
 
+// cell of a coordinate along one axis at the deepest level: floor(x/L 2^21),
+// clamped to [0, 2^21 - 1]; the level-l cell is this >> (21 - l)
+__device__ __forceinline__ uint32_t key_cell(double x, double L)
+{
+    double s = (x / L) * 2097152.0; // 2^21
+    if (!(s >= 0.0)) return 0u;
+    if (s >= 2097151.0) return 2097151u;
+    return (uint32_t)s;
+}
+
 // ---------------------------------------------------------------- wave ops
 __device__ __forceinline__ int lane_id()
 {
@@ -231,8 +241,8 @@ struct GroupBufs {
     int64_t max_chunks;
 };
 hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params *gp,
-                         const sfc_group_params *gp_box, GroupBufs &g, uint32_t *scan_tmp,
-                         DevStatus *st);
+                         const sfc_group_params *gp_box, const int8_t *dlev, GroupBufs &g,
+                         uint32_t *scan_tmp, DevStatus *st);
 
 struct SearchBufs {
     int32_t *cand;    // [cand_cap] candidate supersets of all groups

@@ -53,13 +53,6 @@ __device__ __forceinline__ uint64_t hilbert_key63(uint32_t a0, uint32_t a1, uint
     return (spread3(a0) << 2) | (spread3(a1) << 1) | spread3(a2);
 }
 
-__device__ __forceinline__ uint32_t key_cell(double x, double L)
-{
-    double s = (x / L) * 2097152.0; // 2^21
-    if (!(s >= 0.0)) return 0u;
-    if (s >= 2097151.0) return 2097151u;
-    return (uint32_t)s;
-}
 
 // Keys, the sort payload (input index, with the active flag in bit 31: n <
 // 2^30) and the particle's 64-byte record: the fields are read here once, in

@@ -25,6 +25,7 @@ class StepConfig:
     n_group_max: int = 32
     f: float = 0.5
     chunk: int = 1024
+    level: int = 5  # tree policy: depth of the grouping nodes
     t_cand: int = 2048
     hydro_t_cand: int = 2048
     skin: float = 1.0
@@ -98,7 +99,7 @@ class Pipeline:
         c = self.cfg
         self.ctx.group_ngb_search(self.ps, c.policy, c.n_group_max, c.f, c.chunk,
                                   gp_box=self.gp_box, verify=verify,
-                                  t_cand=t_cand or c.t_cand)
+                                  t_cand=t_cand or c.t_cand, level=c.level)
 
     def density(self):
         self.ctx.density(self.ps, self.dp, self.dout)

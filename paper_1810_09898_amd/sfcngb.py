@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libsfcngb.so")
 
 SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_EHIP, SFC_EOVERFLOW, SFC_EORDER = 0, -1, -2, -3, -4, -5
-POLICY_COUNT, POLICY_PAPER = 0, 1
+POLICY_COUNT, POLICY_PAPER, POLICY_TREE = 0, 1, 2
 KERNEL_CUBIC, KERNEL_WC6 = 0, 1
 ACCUM_F32, ACCUM_F64 = 0, 1
 ST_LIST_OVERFLOW, ST_NODE_OVERFLOW, ST_BAD_INPUT = 1, 2, 4
@@ -53,7 +53,7 @@ class CParticles(C.Structure):
 
 class GroupParams(C.Structure):
     _fields_ = [("policy", C.c_int32), ("n_group_max", C.c_int32), ("f", C.c_double),
-                ("chunk", C.c_int32)]
+                ("chunk", C.c_int32), ("level", C.c_int32)]
 
 
 class Verify(C.Structure):
@@ -281,9 +281,10 @@ class Context:
         self._check(self.L.tree_refit_hmax(self.h, C.byref(a)))
 
     def group_ngb_search(self, p: Particles, policy=POLICY_PAPER, n_group_max=32, f=0.5,
-                         chunk=1024, gp_box=None, verify: Verify | None = None, t_cand=1024):
+                         chunk=1024, gp_box=None, verify: Verify | None = None, t_cand=1024,
+                         level=0):
         a = p.c()
-        gp = GroupParams(policy, n_group_max, f, chunk)
+        gp = GroupParams(policy, n_group_max, f, chunk, level)
         self._check(self.L.group_ngb_search(
             self.h, C.byref(a), None if gp_box is not None else C.byref(gp), _ptr(gp_box),
             C.byref(verify) if verify is not None else None, t_cand))

@@ -123,13 +123,16 @@ def test_octree_matches_oracle(name, n_leaf, request):
     assert np.array_equal(lo[:, 3], t.hmax)
 
 
-@pytest.mark.parametrize("policy,cap,f,chunk", [(1, 16, 0.5, 1024), (1, 64, 0.5, 64),
-                                                (1, 32, 0.3, 4096), (1, 64, 0.8, 256),
-                                                (0, 8, 0.0, 1024), (0, 1, 0.0, 64)])
-def test_groups_match_oracle(policy, cap, f, chunk, plum):
-    say(f"[groups] policy={policy} cap={cap} f={f} chunk={chunk}")
+@pytest.mark.parametrize("policy,cap,f,chunk,level,n_leaf", [
+    (1, 16, 0.5, 1024, 0, 16), (1, 64, 0.5, 64, 0, 16), (1, 32, 0.3, 4096, 0, 16),
+    (1, 64, 0.8, 256, 0, 16), (0, 8, 0.0, 1024, 0, 16), (0, 1, 0.0, 64, 0, 16),
+    (2, 64, 0.0, 1024, 4, 16), (2, 16, 0.0, 256, 6, 16), (2, 64, 0.0, 1024, 7, 128),
+    (2, 64, 0.0, 4096, 0, 16), (2, 32, 0.0, 1024, 21, 8)])
+def test_groups_match_oracle(policy, cap, f, chunk, level, n_leaf, plum):
+    say(f"[groups] policy={policy} cap={cap} f={f} chunk={chunk} level={level} n_leaf={n_leaf}")
     import torch
-    pl = Pipeline(plum, StepConfig(policy=policy, n_group_max=cap, f=f, chunk=chunk))
+    pl = Pipeline(plum, StepConfig(policy=policy, n_group_max=cap, f=f, chunk=chunk, level=level,
+                                   n_leaf=n_leaf))
     pl.sort()
     pl.tree()
     pl.groups()
@@ -141,7 +144,12 @@ def test_groups_match_oracle(policy, cap, f, chunk, plum):
     actg = pl.ctx.ws_view(v.act, A, torch.int32).cpu().numpy()
     ob, keys, perm, s, act = osorted(plum)
     assert np.array_equal(actg, act)
-    og = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], ob, policy, cap, f, chunk)
+    ll = None
+    if policy == oracle.POLICY_TREE:
+        t = oracle.octree(keys, s["x"], s["y"], s["z"], s["h"], ob, n_leaf)
+        ll = oracle.leaf_levels(t, len(s["x"]))
+    og = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], ob, policy, cap, f, chunk,
+                       level=level, leaf_level=ll)
     assert np.array_equal(goff, og)
 
 
@@ -149,13 +157,14 @@ def test_groups_per_box_params(batch):
     import torch
     nb = len(batch.box_L)
     rng = np.random.default_rng(4)
-    pol = rng.integers(0, 2, nb)
+    pol = rng.integers(0, 3, nb)
     cap = rng.integers(1, 65, nb)
     ff = rng.uniform(0.2, 0.9, nb)
     ch = rng.choice([64, 256, 1024], nb)
+    lev = rng.integers(2, 9, nb)
     arr = (S.GroupParams * nb)()
     for b in range(nb):
-        arr[b] = S.GroupParams(int(pol[b]), int(cap[b]), float(ff[b]), int(ch[b]))
+        arr[b] = S.GroupParams(int(pol[b]), int(cap[b]), float(ff[b]), int(ch[b]), int(lev[b]))
     raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
     dev = torch.as_tensor(raw, device="cuda")
     pl = Pipeline(batch, StepConfig(), gp_box=dev)
@@ -167,7 +176,10 @@ def test_groups_per_box_params(batch):
     v = pl.ctx.views()
     goff = pl.ctx.ws_view(v.goff, st["n_groups"] + 1, torch.int32).cpu().numpy()
     ob, keys, perm, s, act = osorted(batch)
-    og = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], ob, pol, cap, ff, 0)
+    t = oracle.octree(keys, s["x"], s["y"], s["z"], s["h"], ob, StepConfig().n_leaf)
+    ll = oracle.leaf_levels(t, len(s["x"]))
+    og = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], ob, pol, cap, ff, 0, level=lev,
+                       leaf_level=ll)
     # per-box chunks: the oracle takes one chunk for all boxes, so compare box by box
     box = ob.box_of()[act]
     ref = []
@@ -176,7 +188,7 @@ def test_groups_per_box_params(batch):
         if len(sel) == 0:
             continue
         g = oracle.groups(act[sel], s["x"], s["y"], s["z"], s["h"], ob, pol[b], cap[b], ff[b],
-                          int(ch[b]))
+                          int(ch[b]), level=int(lev[b]), leaf_level=ll)
         ref.extend((g[:-1] + sel[0]).tolist())
     ref.append(len(act))
     assert np.array_equal(goff, np.array(ref))
@@ -294,7 +306,8 @@ def test_density_h_loop_clustered(plum, plum_ref):
 
 @pytest.mark.parametrize("policy,cap,f,T", [(0, 1, 0.0, 1024), (0, 8, 0.0, 1024),
                                             (1, 16, 0.5, 1024), (1, 64, 0.5, 2048),
-                                            (1, 64, 1.0, 4096), (1, 32, 0.5, 64)])
+                                            (1, 64, 1.0, 4096), (1, 32, 0.5, 64),
+                                            (2, 64, 0.0, 2048)])
 def test_density_independent_of_grouping(policy, cap, f, T, plum, plum_ref):
     """Refinement gives each particle its true neighbours whatever its group,
     and the summation order depends only on the neighbour list: FP32 results

@@ -275,6 +275,61 @@ def test_grouping_greedy_is_maximal():
                 assert not inside
 
 
+def test_tree_grouping_hand_case():
+    """Tree-depth grouping (section "Adaptive Neighbour Recycling"): two
+    clusters of four particles in opposite octants.  Depth 1 gives one group
+    per octant; depth 0 one group; and when the root is itself a leaf (n_leaf
+    >= 8) a depth-1 request still groups the whole leaf."""
+    q = 2.0 ** -4
+    pts = [(q, q, q), (2 * q, q, q), (q, 2 * q, q), (q, q, 2 * q)]
+    pts += [(1 - a, 1 - b, 1 - c) for a, b, c in pts]
+    st = {"x": np.array([p[0] for p in pts]), "y": np.array([p[1] for p in pts]),
+          "z": np.array([p[2] for p in pts]), "h": np.full(8, 0.1)}
+    B = Boxes.single(8)
+    keys, perm, s = oracle.sorted_state(st, B)
+    act = np.arange(8)
+    # depth 3 (cells of 1/8): the first cluster's four particles sit in four
+    # cells (leaves at depth 3), the second cluster's in one cell (x = 7/8 and
+    # 15/16 share cell 7), an internal node of depth 3 with n_leaf = 2
+    for n_leaf, level, want in ((2, 1, [0, 4, 8]), (2, 0, [0, 8]), (8, 1, [0, 8]),
+                                (2, 3, [0, 1, 2, 3, 4, 8])):
+        t = oracle.octree(keys, s["x"], s["y"], s["z"], s["h"], B, n_leaf)
+        ll = oracle.leaf_levels(t, 8)
+        g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, 64, 0.0,
+                          0, level=level, leaf_level=ll)
+        assert list(g) == want, (n_leaf, level)
+    # the cap splits a node's actives
+    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, 3, 0.0, 0,
+                      level=1, leaf_level=oracle.leaf_levels(
+                          oracle.octree(keys, s["x"], s["y"], s["z"], s["h"], B, 2), 8))
+    assert list(g) == [0, 3, 4, 7, 8]
+
+
+@pytest.mark.parametrize("level,n_leaf", [(2, 16), (4, 8), (6, 16), (9, 4)])
+def test_tree_grouping_equals_node_ranges(level, n_leaf):
+    """The groups are the actives of the tree's own nodes: for every node of
+    depth `level`, and every leaf shallower than that, its active particles
+    (a contiguous run of the curve-ordered actives) form one group, split
+    only by the cap.  Built here from the octree's node ranges, not from
+    cell arithmetic."""
+    keys, s, B = _rand_sorted(3000, 11, clustered=True)
+    act = np.nonzero(np.random.default_rng(3).random(3000) < 0.4)[0].astype(np.int32)
+    t = oracle.octree(keys, s["x"], s["y"], s["z"], s["h"], B, n_leaf)
+    cap = 7
+    want = []
+    pos = {int(i): k for k, i in enumerate(act)}
+    for k in range(len(t.first)):
+        if t.level[k] == level or (t.leaf[k] and t.level[k] < level):
+            mem = [pos[i] for i in range(t.first[k], t.first[k] + t.count[k]) if i in pos]
+            if mem:
+                assert mem == list(range(mem[0], mem[-1] + 1))
+                want += mem[::cap]
+    want = sorted(want) + [len(act)]
+    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, cap, 0.0, 0,
+                      level=level, leaf_level=oracle.leaf_levels(t, 3000))
+    assert list(g) == want
+
+
 # --------------------------------------------------------------------------
 # Neighbour sets: exact lattice counts and hand-counted cases
 # --------------------------------------------------------------------------
