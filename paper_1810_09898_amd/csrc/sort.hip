@@ -241,55 +241,104 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
     hist[(int64_t)t * ntiles + blockIdx.x] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
 }
 
+// Stable scatter of one tile: wave w owns the tile's keys [1024 w, 1024 w +
+// 1024) and ranks them round by round (64 keys, eight ballots find the lanes
+// with the same digit) against a wave-private running count per digit; the
+// tile-local position of a key is then its digit's start in the tile + the
+// counts of the earlier waves + its rank in the wave.  Keys go to LDS in
+// that order and leave in it, so consecutive threads write consecutive
+// addresses of a digit's run.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint32_t *__restrict__ bin, uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
     uint32_t *__restrict__ bout, int64_t n, int shift, int box_pass,
     const uint32_t *__restrict__ offs, int ntiles)
 {
+    constexpr int PER_WAVE = RS_TILE / (RS_THREADS / 64); // 1024 keys
+    constexpr int WR = PER_WAVE / 64;                     // 16 rounds
+    __shared__ uint64_t lk[RS_TILE];
+    __shared__ uint32_t lv[RS_TILE];
+    __shared__ uint32_t lb[RS_TILE];
+    __shared__ uint32_t cntw[RS_THREADS / 64][256];
+    __shared__ uint32_t dstart[256];
     __shared__ uint32_t gbase[256];
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wc[4][256];
-    int t = threadIdx.x, w = t >> 6;
+    __shared__ uint32_t wsum[RS_THREADS / 64];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int tile_n = (int)(n - base < RS_TILE ? n - base : RS_TILE);
     gbase[t] = offs[(int64_t)t * ntiles + blockIdx.x];
-    run[t] = 0;
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ROUNDS; r++) {
-        for (int k = 0; k < 4; k++) wc[k][t] = 0;
-        __syncthreads();
-        int64_t i = base + r * RS_THREADS + t;
-        bool valid = i < n;
-        uint64_t kk = valid ? kin[i] : 0ull;
-        uint32_t vv = valid ? vin[i] : 0u;
-        uint32_t bb = (valid && bin) ? bin[i] : 0u;
-        uint32_t d = box_pass ? (bb >> shift) & 255u : (uint32_t)(kk >> shift) & 255u;
+    for (int k = 0; k < RS_THREADS / 64; k++) cntw[k][t] = 0;
+    __syncthreads();
+    uint64_t kk[WR];
+    uint32_t vv[WR], bb[WR], dd[WR], rk[WR];
+#pragma unroll
+    for (int r = 0; r < WR; r++) {
+        const int li = w * PER_WAVE + r * 64 + lane;
+        const bool valid = li < tile_n;
+        kk[r] = valid ? kin[base + li] : 0ull;
+        vv[r] = valid ? vin[base + li] : 0u;
+        bb[r] = (valid && bin) ? bin[base + li] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < WR; r++) {
+        const int li = w * PER_WAVE + r * 64 + lane;
+        const bool valid = li < tile_n;
+        const uint32_t d = box_pass ? (bb[r] >> shift) & 255u : (uint32_t)(kk[r] >> shift) & 255u;
         uint64_t peers = ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            bool bit = (d >> b) & 1u;
-            uint64_t m = ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = ballot(bit);
             peers &= bit ? m : ~m;
         }
-        int rank = mbcnt(peers);
-        if (valid && rank == 0) wc[w][d] = (uint32_t)popc64(peers);
-        __syncthreads();
-        {
-            uint32_t c0 = wc[0][t], c1 = wc[1][t], c2 = wc[2][t], c3 = wc[3][t];
-            uint32_t r0 = run[t];
-            wc[0][t] = r0;
-            wc[1][t] = r0 + c0;
-            wc[2][t] = r0 + c0 + c1;
-            wc[3][t] = r0 + c0 + c1 + c2;
-            run[t] = r0 + c0 + c1 + c2 + c3;
+        const int rank = mbcnt(peers);
+        const uint32_t before = valid ? cntw[w][d] : 0u;
+        wave_lds_sync();
+        if (valid && rank == 0) cntw[w][d] = before + (uint32_t)popc64(peers);
+        wave_lds_sync();
+        dd[r] = d;
+        rk[r] = before + (uint32_t)rank;
+    }
+    __syncthreads();
+    // digit d = thread t: counts of the waves before each wave, the tile
+    // total, and its exclusive scan over the digits
+    uint32_t tot = 0;
+    for (int k = 0; k < RS_THREADS / 64; k++) {
+        const uint32_t c = cntw[k][t];
+        cntw[k][t] = tot;
+        tot += c;
+    }
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t woff = 0;
+    for (int k = 0; k < w; k++) woff += wsum[k];
+    dstart[t] = woff + inc - tot;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < WR; r++) {
+        const int li = w * PER_WAVE + r * 64 + lane;
+        if (li < tile_n) {
+            const uint32_t lp = dstart[dd[r]] + cntw[w][dd[r]] + rk[r];
+            lk[lp] = kk[r];
+            lv[lp] = vv[r];
+            lb[lp] = bb[r];
         }
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = gbase[d] + wc[w][d] + (uint32_t)rank;
-            kout[pos] = kk;
-            vout[pos] = vv;
-            if (bout) bout[pos] = bb;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    for (int j = t; j < tile_n; j += RS_THREADS) {
+        const uint64_t k = lk[j];
+        const uint32_t bx = lb[j];
+        const uint32_t d = box_pass ? (bx >> shift) & 255u : (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = gbase[d] + (uint32_t)j - dstart[d];
+        kout[pos] = k;
+        vout[pos] = lv[j];
+        if (bout) bout[pos] = bx;
     }
 }
 

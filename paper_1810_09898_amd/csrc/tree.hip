@@ -228,57 +228,43 @@ __device__ __forceinline__ void box_store(const TreeDev &t, int id, const NodeBo
     }
 }
 
-// Leaves: every wave takes 64 node ids at a time; their leaves are reduced
-// over their particles eight at a time, each by a group of eight lanes that
-// strides through the particle range.
+// Leaves: a group of eight lanes per node id (grid-stride); a leaf's group
+// strides through its particles, eight at a time.
 __global__ void k_tree_leaves(const PartDev p, const TreeDev t, const DevStatus *st_in,
                               DevStatus *st, int with_bbox)
 {
     const int nn = min(st_in->n_nodes, t.capacity);
     const int lane = lane_id();
-    const int grp = lane >> 3, sub = lane & 7;
+    const int sub = lane & 7;
     const bool bbox = with_bbox != 0;
-    const int nw = (int)(gridDim.x * blockDim.x) >> 6;
-    for (int base = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; base < nn;
-         base += nw * 64) {
-        const int id = base + lane;
+    const int ng = (int)(gridDim.x * blockDim.x) >> 3;
+    // every lane runs the same number of rounds, so the group reductions
+    // below always see all their lanes active
+    const int rounds = (nn + ng - 1) / ng;
+    int id = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
+    for (int r = 0; r < rounds; r++, id += ng) {
         const int4 inf = id < nn ? t.info[id] : make_int4(0, 0, 0, 0);
-        uint64_t m = ballot(id < nn && (inf.w >> 8));
-        while (m) {
-            // the next (up to) eight leaves, one per lane group
-            int mine = -1;
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const int s = ctz64(m);
-                if (m) m &= m - 1;
-                if (grp == q && s < 64) mine = s;
+        const bool leaf = id < nn && (inf.w >> 8);
+        const int first = inf.x, cnt = leaf ? inf.y : 0;
+        const int b = p.nb > 1 && leaf ? box_of(p.box_off, p.nb, first) : 0;
+        const double L = p.box_L[b];
+        NodeBox bx = box_empty();
+        bool bad = false;
+        for (int i = first + sub; i < first + cnt; i += 8) {
+            const double hh = p.h[i];
+            bx.hm = fmax(bx.hm, hh);
+            bad |= !(hh > 0.0);
+            if (bbox) {
+                const double x = p.x[i], y = p.y[i], z = p.z[i];
+                bx.lx = fmin(bx.lx, x); bx.hx = fmax(bx.hx, x);
+                bx.ly = fmin(bx.ly, y); bx.hy = fmax(bx.hy, y);
+                bx.lz = fmin(bx.lz, z); bx.hz = fmax(bx.hz, z);
+                bad |= !(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L);
             }
-            // both reads with every lane active: a cross-lane read from a lane
-            // that is switched off returns 0
-            const int src = mine < 0 ? 0 : mine;
-            const int first = __shfl(inf.x, src, 64);
-            const int cnt_s = __shfl(inf.y, src, 64);
-            const int cnt = mine < 0 ? 0 : cnt_s;
-            const int b = p.nb > 1 && mine >= 0 ? box_of(p.box_off, p.nb, first) : 0;
-            const double L = p.box_L[b];
-            NodeBox bx = box_empty();
-            bool bad = false;
-            for (int i = first + sub; i < first + cnt; i += 8) {
-                const double hh = p.h[i];
-                bx.hm = fmax(bx.hm, hh);
-                bad |= !(hh > 0.0);
-                if (bbox) {
-                    const double x = p.x[i], y = p.y[i], z = p.z[i];
-                    bx.lx = fmin(bx.lx, x); bx.hx = fmax(bx.hx, x);
-                    bx.ly = fmin(bx.ly, y); bx.hy = fmax(bx.hy, y);
-                    bx.lz = fmin(bx.lz, z); bx.hz = fmax(bx.hz, z);
-                    bad |= !(x >= 0.0 && x < L && y >= 0.0 && y < L && z >= 0.0 && z < L);
-                }
-            }
-            if (ballot(bad) != 0ull && lane == 0) atomicOr(&st->flags, SFC_ST_BAD_INPUT);
-            box_reduce<1, 8>(bx, bbox);
-            if (sub == 0 && mine >= 0) box_store(t, base + mine, bx, bbox);
         }
+        if (ballot(bad) != 0ull && lane == 0) atomicOr(&st->flags, SFC_ST_BAD_INPUT);
+        box_reduce<1, 8>(bx, bbox);
+        if (sub == 0 && leaf) box_store(t, id, bx, bbox);
     }
 }
 
@@ -367,7 +353,9 @@ hipError_t launch_tree_refit(hipStream_t s, const PartDev &p, TreeDev &t, bool b
         k_tree_nchild<<<gnodes, 256, 0, s>>>(t, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    k_tree_leaves<<<gnodes, 256, 0, s>>>(p, t, st, st, bbox ? 1 : 0);
+    // eight lanes per node id: up to 8192 workgroups of 32 node ids
+    const int64_t gl = (8 * (int64_t)t.capacity + 255) / 256;
+    k_tree_leaves<<<(unsigned)(gl < 8192 ? gl : 8192), 256, 0, s>>>(p, t, st, st, bbox ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // level 21 holds leaves only; levels 20 .. 0 in three-level steps
     for (int level = SFC_KEY_BITS - 3; level >= 0; level -= 3) {
