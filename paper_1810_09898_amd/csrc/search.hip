@@ -820,7 +820,7 @@ __device__ __forceinline__ void solo_walk(const Geom &g, const MemLds &S, const 
 
 // FIFO entries: a neighbour and what the filter already knows of the pair.
 // Density: the FP32 r^2 of the FP32 positions (r2_f32).  Hydro: the
-// minimum-image x_i - x_j rounded to FP32.  Every path that pushes a pair
+// minimum-image x_i - x_j of the FP32 positions.  Every path that pushes a pair
 // computes these the same way, so a particle's sums do not depend on the
 // path (group superset, own superset or own walk).
 struct DEnt {
@@ -1078,7 +1078,11 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
             const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
             const double hm = fmax(hi, p.h);
             hit = valid && (j != i) && (r2 < hm * hm);
-            q.push(hit, HEnt{j, (float)dx, (float)dy, (float)dz}, *consume);
+            const float Lf = (float)L;
+            q.push(hit,
+                   HEnt{j, fold32((float)xi - (float)p.x, Lf), fold32((float)yi - (float)p.y, Lf),
+                        fold32((float)zi - (float)p.z, Lf)},
+                   *consume);
         }
     }
 };
@@ -1317,8 +1321,9 @@ struct HydroK {
     GroupArg ga;
     CandArg ca;
     const float *m, *vx, *vy, *vz, *u, *rho, *fgrad;
-    const float4 *pa; // per particle: m, vx, vy, vz
-    const float4 *pb; // per particle: rho, f P / rho^2, sound speed, h
+    const float4 *pa;   // per particle: m, vx, vy, vz
+    const float4 *pb;   // per particle: rho, f P / rho^2, sound speed, h
+    const float4 *pos4; // per particle: FP32 x, y, z, m
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
@@ -1480,13 +1485,16 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
                              const float *__restrict__ vy, const float *__restrict__ vz,
                              const float *__restrict__ rho, const float *__restrict__ fgrad,
                              const float *__restrict__ u, const double *__restrict__ h,
-                             double gamma, float4 *__restrict__ pa, float4 *__restrict__ pb)
+                             const double *__restrict__ x, const double *__restrict__ y,
+                             const double *__restrict__ z, double gamma, float4 *__restrict__ pa,
+                             float4 *__restrict__ pb, float4 *__restrict__ pos4)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double gm1 = gamma - 1.0;
     double uu = u[i];
     pa[i] = make_float4(m[i], vx[i], vy[i], vz[i]);
+    pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], m[i]);
     pb[i] = make_float4(rho[i], (float)(fgrad[i] * gm1 * uu / (double)rho[i]),
                         (float)sqrt(gamma * gm1 * uu), (float)h[i]);
 }
@@ -1518,6 +1526,11 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
         const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
         HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, wrap);
         FifoH q{(HEnt *)S.fifo, 0};
+        // the filter decides r < max(h_i, h_j) on FP32 positions and h (as
+        // the density count pass does, band widened for the FP32 h and the
+        // FP32 band arithmetic), and in FP64 inside the band
+        const float xf = (float)M.xi, yf = (float)M.yi, zf = (float)M.zi, Lf = (float)M.bx.L,
+                    hf = (float)M.h;
         const int nc = M.s.nc;
         const int nch = (nc + 63) >> 6;
         const int32_t *cg = k.ca.cand + M.s.c0;
@@ -1532,28 +1545,40 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
                 v[u] = ((c0 + u) << 6) + lane < nc;
                 j[u] = jn[u];
             }
-            double xj[UNR], yj[UNR], zj[UNR], hj[UNR];
+            float4 pj[UNR];
+            float hj[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-                xj[u] = k.g.x[j[u]];
-                yj[u] = k.g.y[j[u]];
-                zj[u] = k.g.z[j[u]];
-                hj[u] = k.g.h[j[u]];
+                pj[u] = k.pos4[j[u]];
+                hj[u] = k.pb[j[u]].w;
             }
 #pragma unroll
             for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
 #pragma unroll
             for (int u = 0; u < UNR; u++) {
-                // x_i - x_j (the force direction), folded when pairs need it
-                double dx = M.xi - xj[u], dy = M.yi - yj[u], dz = M.zi - zj[u];
+                // x_i - x_j (the force direction) of the FP32 positions, folded
+                // when pairs need it
+                float dx = xf - pj[u].x, dy = yf - pj[u].y, dz = zf - pj[u].z;
                 if (wrap) {
-                    dx = fold(dx, M.bx.L);
-                    dy = fold(dy, M.bx.L);
-                    dz = fold(dz, M.bx.L);
+                    dx = fold32(dx, Lf);
+                    dy = fold32(dy, Lf);
+                    dz = fold32(dz, Lf);
                 }
-                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                const double hm = fmax(M.h, hj[u]);
-                q.push(v[u] && j[u] != M.i && r2 < hm * hm, HEnt{j[u], (float)dx, (float)dy, (float)dz}, hp);
+                const float r2f = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                const float hmf = fmaxf(hf, hj[u]);
+                const float hm2f = hmf * hmf;
+                const float E = 0x1p-19f * __builtin_fmaf(Lf, hmf, hm2f);
+                bool hit = r2f < hm2f - E;
+                const bool amb = v[u] && !hit && !(r2f > hm2f + E);
+                if (ballot(amb)) { // inside the band: the FP64 test decides
+                    if (amb) {
+                        const int jj = j[u];
+                        const double hm = fmax(M.h, k.g.h[jj]);
+                        hit = r2_of(k.g.x[jj], k.g.y[jj], k.g.z[jj], M.xi, M.yi, M.zi, M.bx.L,
+                                    wrap) < hm * hm;
+                    }
+                }
+                q.push(v[u] && j[u] != M.i && hit, HEnt{j[u], dx, dy, dz}, hp);
             }
         }
         q.flush(hp);
@@ -1849,8 +1874,8 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
 {
     const sfc_hydro_params &hp = a.hp;
     k_hydro_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.m, p.vx, p.vy, p.vz, p.rho,
-                                                               p.fgrad, p.u, p.h, hp.gamma, sb.pa,
-                                                               sb.pb);
+                                                               p.fgrad, p.u, p.h, p.x, p.y, p.z,
+                                                               hp.gamma, sb.pa, sb.pb, sb.pos4);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_walk(s, p, t, g, sb, st, hp.t_cand, 1.0, 1);
@@ -1869,6 +1894,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.fgrad = p.fgrad;
     k.pa = sb.pa;
     k.pb = sb.pb;
+    k.pos4 = sb.pos4;
     k.out = a.out;
     k.st = st;
     k.gamma = hp.gamma;
