@@ -30,6 +30,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # wave64 VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
 VALU_PEAK_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
+# the same in lane instructions (16 lanes per SIMD per cycle): 39.3e12/s, the
+# non-packed FP32 / FP64 vector rate (78.6 TFLOP/s counting an FMA as two)
+ALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# algorithmic lane instructions per unit of work: a member x candidate test
+# of the filter, a density pair sum, a hydro pair sum
+TEST_OPS, DENS_PAIR_OPS, HYD_PAIR_OPS = 10, 30, 80
 # algorithmic bytes per candidate record and per active (x, y, z FP64 + m FP32;
 # hydro adds h FP64 and v, rho, P f/rho^2, c FP32) and per active particle of
 # inputs read plus outputs written
@@ -178,16 +184,23 @@ def main():
         }
         del ung
 
-    # roofline of the dominant call (algorithmic bytes / its device time):
-    # density = walk kernel + per-particle filter/sum kernel; hydro = record
-    # kernel + max-h refit + walk kernel + per-particle kernel
+    # roofline of the dominant call: density = walk kernel + per-particle
+    # filter/sum kernel; hydro = record kernel + max-h refit + walk kernel +
+    # per-particle kernel.  The calls are bound by vector ALU issue (the
+    # counters show ~65 % VALU issue against ~10 % of HBM), so the roofline is
+    # the ALU one: algorithmic lane instructions (tests and pairs counted by
+    # the kernels x the per-unit costs) / the call's time, against the chip's
+    # lane-instruction rate.  The HBM view (algorithmic bytes) rides along.
     dens_bytes = st_d["sum_cand"] * DENS_BC + A * DENS_BIO
     hyd_bytes = st_h["sum_cand"] * HYD_BC + A * HYD_BIO
+    dens_ops = st_d["sum_tests"] * TEST_OPS + st_d["sum_pairs"] * DENS_PAIR_OPS
+    hyd_ops = st_h["sum_tests"] * TEST_OPS + st_h["sum_pairs"] * HYD_PAIR_OPS
     if ph["hydro"] >= ph["density"]:
-        kname, kbytes, kms = "hydro_force", hyd_bytes, ph["hydro"]
+        kname, kbytes, kops, kms = "hydro_force", hyd_bytes, hyd_ops, ph["hydro"]
     else:
-        kname, kbytes, kms = "density", dens_bytes, ph["density"]
+        kname, kbytes, kops, kms = "density", dens_bytes, dens_ops, ph["density"]
     achieved = kbytes / (kms * 1e-3) / 1e9
+    ach_ops = kops / (kms * 1e-3) / 1e12
     traffic, valu = None, None
     if os.path.exists(PMC_FILE):
         pm = json.load(open(PMC_FILE))
@@ -199,11 +212,24 @@ def main():
                 valu = {"insts": insts, "achieved": round(insts / (kms * 1e-3), 1),
                         "peak": VALU_PEAK_WAVE_INSTS, "unit": "wave64 VALU insts/s",
                         "frac": round(insts / (kms * 1e-3) / VALU_PEAK_WAVE_INSTS, 4)}
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+    peak_t = ALU_PEAK_LANE_OPS / 1e12
+    roof = {"bound": "alu", "achieved": round(ach_ops, 3), "peak": round(peak_t, 2),
+            "unit": "T lane-instructions/s", "frac": round(ach_ops / peak_t, 4),
+            "traffic": traffic, "kernel": kname,
             "kernels": ("k_walk + k_density" if kname == "density"
                         else "k_hydro_prep + refit + k_walk + k_hydro"),
-            "algorithmic_bytes": int(kbytes), "launch_ms": round(kms, 4), "valu": valu}
+            "algorithmic_ops": int(kops),
+            "ops_model": f"{TEST_OPS} per member x candidate test, {DENS_PAIR_OPS} per density "
+                         f"pair, {HYD_PAIR_OPS} per hydro pair",
+            "launch_ms": round(kms, 4),
+            "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(kbytes)},
+            "other_call": {"name": "hydro_force" if kname == "density" else "density",
+                           "launch_ms": round(ph["hydro"] if kname == "density" else ph["density"], 4),
+                           "alu_frac": round((hyd_ops if kname == "density" else dens_ops)
+                                             / ((ph["hydro"] if kname == "density" else ph["density"])
+                                                * 1e-3) / ALU_PEAK_LANE_OPS, 4)},
+            "valu": valu}
 
     cpu = None
     if not args.no_cpu_baseline:

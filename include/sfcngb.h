@@ -263,6 +263,8 @@ typedef struct {
     int64_t sum_cand;        /* sum of group superset sizes (since bind) */
     int64_t n_walks;         /* tree walks (since bind) */
     int64_t sum_iters;       /* h evaluations (since bind) */
+    int64_t sum_tests;       /* member x superset-candidate tests of the filters (since bind) */
+    int64_t sum_pairs;       /* neighbour pairs summed by density and hydro (since bind) */
 } sfc_status;
 
 /* Synchronise the stream and copy the status block to *out.  Returns

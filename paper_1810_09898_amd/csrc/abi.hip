@@ -464,6 +464,8 @@ int sfc_status_read(sfc_ctx *ctx, sfc_status *out)
     out->sum_cand = (int64_t)s.sum_cand;
     out->n_walks = (int64_t)s.n_walks;
     out->sum_iters = (int64_t)s.sum_iters;
+    out->sum_tests = (int64_t)s.sum_tests;
+    out->sum_pairs = (int64_t)s.sum_pairs;
     if (s.flags & (SFC_ST_LIST_OVERFLOW | SFC_ST_NODE_OVERFLOW | SFC_ST_GUARD))
         return fail(ctx, SFC_EOVERFLOW, "device capacity or loop limit exceeded (flags 0x%x)", s.flags);
     return SFC_OK;

@@ -132,6 +132,8 @@ struct DevStatus {
     unsigned long long sum_cand;
     unsigned long long n_walks;
     unsigned long long sum_iters;
+    unsigned long long sum_tests;
+    unsigned long long sum_pairs;
     int32_t pad[2];
     // Per-pass counters of the search kernels, one per eighth of the work
     // items, each on its own 128-byte line so that the eighths do not

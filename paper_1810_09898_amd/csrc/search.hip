@@ -127,7 +127,7 @@ __device__ __forceinline__ unsigned long long uni_u64(unsigned long long v)
 // serialise the whole grid on one address.
 struct WaveStats {
     uint32_t walks = 0, overflow = 0, deferred = 0, iters = 0, not_conv = 0;
-    unsigned long long cand = 0;
+    unsigned long long cand = 0, tests = 0, pairs = 0;
     __device__ __forceinline__ void flush(DevStatus *st) const
     {
         if (lane_id() != 0) return;
@@ -137,6 +137,8 @@ struct WaveStats {
         if (deferred) atomicAdd(&st->n_deferred, (unsigned long long)deferred);
         if (iters) atomicAdd(&st->sum_iters, (unsigned long long)iters);
         if (not_conv) atomicAdd(&st->n_not_converged, (unsigned long long)not_conv);
+        if (tests) atomicAdd(&st->sum_tests, tests);
+        if (pairs) atomicAdd(&st->sum_pairs, pairs);
     }
 };
 
@@ -1163,6 +1165,7 @@ __device__ void dens_write(const DensK &k, int i, double h, int nn, int it, bool
                            const DensPair<KER, ACC> &pp, WaveStats &ws)
 {
     ws.iters += (uint32_t)it;
+    ws.pairs += (unsigned)nn;
     if (!conv) ws.not_conv++;
     double Sw = (double)wave_sum_f_or_d(pp.sw.value());
     double Sd = (double)wave_sum_f_or_d(pp.sd.value());
@@ -1224,13 +1227,15 @@ namespace {
 // max_iter evaluations), 0 when h has outgrown the superset (h + d > cov);
 // the masks of the last evaluation stay in LDS
 __device__ __forceinline__ int iterate(const DensK &k, const Member &M, const MemLds &S, double &h,
-                                       double &lo, double &hi, int &it, int &nn, bool &conv)
+                                       double &lo, double &hi, int &it, int &nn, bool &conv,
+                                       WaveStats &ws)
 {
     const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
     bool first = true;
     while (it < k.max_iter) {
         if (!(h + M.d <= M.s.cov)) return 0;
         nn = count_pass(k.g, k.pos4, k.ca.cand, M, h, wrap, S, first);
+        ws.tests += (unsigned)M.s.nc;
         first = false;
         it++;
         if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
@@ -1293,7 +1298,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
         bool conv = false, done = false;
         bool usable = (M.s.flags & GSUP_SOLO) == 0;
         for (int round = 0; round < 4; round++) {
-            if (usable && iterate(k, M, S, h, lo, hi, it, nn, conv)) {
+            if (usable && iterate(k, M, S, h, lo, hi, it, nn, conv, ws)) {
                 done = true;
                 break;
             }
@@ -1534,6 +1539,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
         const int nc = M.s.nc;
         const int nch = (nc + 63) >> 6;
         const int32_t *cg = k.ca.cand + M.s.c0;
+        ws.tests += (unsigned)nc;
         int jn[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; u++) jn[u] = cg[min((u << 6) + lane, nc - 1)];
@@ -1578,7 +1584,9 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
                                     wrap) < hm * hm;
                     }
                 }
-                q.push(v[u] && j[u] != M.i && hit, HEnt{j[u], dx, dy, dz}, hp);
+                const bool pair = v[u] && j[u] != M.i && hit;
+                ws.pairs += (unsigned)popc64(ballot(pair));
+                q.push(pair, HEnt{j[u], dx, dy, dz}, hp);
             }
         }
         q.flush(hp);

@@ -86,7 +86,8 @@ class Status(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("n_nodes", C.c_int32), ("n_active", C.c_int32),
                 ("n_groups", C.c_int32), ("n_deferred", C.c_int64), ("n_overflow", C.c_int64),
                 ("n_not_converged", C.c_int64), ("sum_cand", C.c_int64),
-                ("n_walks", C.c_int64), ("sum_iters", C.c_int64)]
+                ("n_walks", C.c_int64), ("sum_iters", C.c_int64), ("sum_tests", C.c_int64),
+                ("sum_pairs", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
