@@ -426,7 +426,8 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, V &vi
 constexpr int LCAP = 256;
 
 template <class V>
-__device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int *lb, V &visit)
+__device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int *lb, int *mk,
+                            V &visit)
 {
     const int lane = lane_id();
     const int entry = uni(walk_entry(g, uni(root), B));
@@ -455,14 +456,20 @@ __device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int
             const int pre = incl - cnt;
             int carry = 0;
             for (int b0 = 0; b0 < total; b0 += 64) {
-                int own = carry;
-                uint64_t sm = ballot(cnt > 0 && pre >= b0 && pre < b0 + 64);
-                for (int r = 0; r < 65 && sm; r++) {
-                    const int ln = ctz64(sm);
-                    sm &= sm - 1ull;
-                    const int off = uni(readlane_i(pre, ln)) - b0;
-                    if (lane >= off) own = ln;
+                // owner of each slot of this batch: the last item whose first
+                // slot is at or before it (items in ascending order, distinct
+                // first slots), by a prefix maximum over marks in LDS
+                mk[lane] = -1;
+                wave_lds_sync();
+                if (cnt > 0 && pre >= b0 && pre < b0 + 64) mk[pre - b0] = lane;
+                wave_lds_sync();
+                int own = max(mk[lane], carry);
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(own, o, 64);
+                    if (lane >= o) own = max(own, t);
                 }
+                wave_lds_sync();
                 carry = uni(readlane_i(own, 63));
                 const bool valid = b0 + lane < total;
                 const int oit = __shfl(it, own, 64);
@@ -645,14 +652,13 @@ __global__ void k_reset_pass(DevStatus *st)
     }
 }
 
-// One wave per group: the walk, the superset into the global buffer, the
-// group record and the member -> group map.
+// One wave per group: the walk, the superset straight into the global
+// buffer, the group record and the member -> group map.
 __global__ __launch_bounds__(64) void k_walk(WalkK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const int T = k.ga.T;
-    int *cand = (int *)lds_raw;
-    int *lst = cand + T; // [2 * LCAP]: item lists of the level walk
+    int *lst = (int *)lds_raw; // [2 * LCAP + 64]: item lists of the level walk, owner marks
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
     Queue wq = queue_open(k.st->qctr, G);
@@ -694,29 +700,32 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         const int nowrap = cx - rad >= 0.0 && cx + rad < bx.L && cy - rad >= 0.0 &&
                            cy + rad < bx.L && cz - rad >= 0.0 && cz + rad < bx.L;
         Ball B{cx, cy, cz, bx.L, sq(cov * INFL), R, H, k.hydro, nowrap};
-        AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, cand, T, 0, false, false, B, nowrap ? rad : 0.0};
-        if (!walk_levels(k.g, bx.root, B, lst, lst + LCAP, ap)) // list too long: window walk
-            walk(k.g, bx.root, bx.root_end, B, ap, k.st);
-        const int nc = uni(ap.n);
+        // the superset goes straight to the wave's current chunk of the
+        // buffer, which must hold a full tile (a new chunk otherwise; the
+        // rest of the old one stays unused)
+        if (ck_cur >= 0 && ck_end - ck_cur < T) {
+            const int csz = max(T, CHUNK);
+            const int64_t base = cand_alloc(k.st, k.ca, blockIdx.x & 7, csz);
+            ck_cur = base;
+            ck_end = base < 0 ? base : base + csz;
+        }
         int flags = 0;
         int64_t c0 = 0;
-        if (uni_b(ap.over)) {
+        int nc = 0;
+        const bool walked = ck_cur >= 0;
+        if (!walked) { // the buffer is used up: the members walk on their own
             flags = GSUP_SOLO;
         } else {
-            // the wave's current chunk of the buffer; a new chunk when it is full
-            if (ck_cur + nc > ck_end) {
-                const int csz = max(nc, CHUNK);
-                const int64_t base = cand_alloc(k.st, k.ca, blockIdx.x & 7, csz);
-                ck_cur = base;
-                ck_end = base < 0 ? base : base + csz;
-            }
-            if (ck_cur < 0) {
+            AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + ck_cur, T, 0, false, false, B,
+                          nowrap ? rad : 0.0};
+            if (!walk_levels(k.g, bx.root, B, lst, lst + LCAP, lst + 2 * LCAP, ap)) // list too long: window walk
+                walk(k.g, bx.root, bx.root_end, B, ap, k.st);
+            nc = uni(ap.n);
+            if (uni_b(ap.over)) {
                 flags = GSUP_SOLO;
             } else {
                 c0 = ck_cur;
                 ck_cur += nc;
-                wave_lds_sync();
-                for (int s = lane; s < nc; s += 64) k.ca.cand[c0 + s] = cand[s];
                 if (pair_wrap(uni_b(ap.folded), ap.ext, mfold, mext, bx.L)) flags |= GSUP_WRAP;
             }
         }
@@ -731,8 +740,8 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
             sp.flags = flags;
             k.ca.sup[g] = sp;
         }
-        ws.walks++;
-        ws.cand += (unsigned long long)nc;
+        if (walked) ws.walks++;
+        if (!(flags & GSUP_SOLO)) ws.cand += (unsigned long long)nc;
         if (flags & GSUP_SOLO) ws.overflow++;
         if (mem) k.ca.grp[a + lane] = g;
         wave_lds_sync();
@@ -816,7 +825,8 @@ __device__ __forceinline__ void solo_walk(const Geom &g, const MemLds &S, const 
                                           const Ball &B, V &visit, DevStatus *st)
 {
     int *lst = (int *)S.r2c;
-    if (S.rc >= 2 * LCAP && walk_levels(g, M.bx.root, B, lst, lst + LCAP, visit)) return;
+    if (S.rc >= 2 * LCAP + 64 && walk_levels(g, M.bx.root, B, lst, lst + LCAP, lst + 2 * LCAP, visit))
+        return;
     walk(g, M.bx.root, M.bx.root_end, B, visit, st);
 }
 
@@ -1814,7 +1824,7 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.st = st;
     k.skin = skin;
     k.hydro = hydro;
-    const size_t lds = (size_t)4 * T + (size_t)4 * 2 * LCAP;
+    const size_t lds = (size_t)4 * (2 * LCAP + 64);
     return launch_persistent(k_walk, s, k, 64, lds, sb.cu_count, p.n);
 }
 } // namespace
