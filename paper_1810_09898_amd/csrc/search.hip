@@ -1343,7 +1343,7 @@ struct HydroK {
     const float *m, *vx, *vy, *vz, *u, *rho, *fgrad;
     const float4 *pa;   // per particle: m, vx, vy, vz
     const float4 *pb;   // per particle: rho, f P / rho^2, sound speed, h
-    const float4 *pos4; // per particle: FP32 x, y, z, m
+    const float4 *pos4; // per particle: FP32 x, y, z, h
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
@@ -1515,7 +1515,7 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
     double gm1 = gamma - 1.0;
     double uu = u[i];
     pa[i] = make_float4(m[i], vx[i], vy[i], vz[i]);
-    pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], m[i]);
+    pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], (float)h[i]);
     pb[i] = make_float4(rho[i], (float)(fgrad[i] * gm1 * uu / (double)rho[i]),
                         (float)sqrt(gamma * gm1 * uu), (float)h[i]);
 }
@@ -1567,13 +1567,9 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
                 v[u] = ((c0 + u) << 6) + lane < nc;
                 j[u] = jn[u];
             }
-            float4 pj[UNR];
-            float hj[UNR];
+            float4 pj[UNR]; // x, y, z, h
 #pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                pj[u] = k.pos4[j[u]];
-                hj[u] = k.pb[j[u]].w;
-            }
+            for (int u = 0; u < UNR; u++) pj[u] = k.pos4[j[u]];
 #pragma unroll
             for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
 #pragma unroll
@@ -1587,7 +1583,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(
                     dz = fold32(dz, Lf);
                 }
                 const float r2f = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                const float hmf = fmaxf(hf, hj[u]);
+                const float hmf = fmaxf(hf, pj[u].w);
                 const float hm2f = hmf * hmf;
                 const float E = 0x1p-19f * __builtin_fmaf(Lf, hmf, hm2f);
                 bool hit = r2f < hm2f - E;
