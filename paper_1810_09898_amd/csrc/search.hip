@@ -310,8 +310,8 @@ template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4
             const int p0 = __shfl(pre, own, 64);
             j[u] = f + (qc - p0);
         }
-        const Pos p0 = visit.fetch(j[0]);
-        Pos p1 = p0;
+        const auto p0 = visit.fetch(j[0]);
+        auto p1 = p0;
         if (two) p1 = visit.fetch(j[1]);
         visit.take(j[0], t0 + lane < total, p0);
         if (two) visit.take(j[1], t0 + 64 + lane < total, p1);
@@ -513,6 +513,15 @@ __device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int
     return true;
 }
 
+// minimum-image fold in FP32 (the FP32 copies of the positions)
+__device__ __forceinline__ float fold32(float d, float L)
+{
+    const float half = 0.5f * L;
+    if (d >= half) d = d - L;
+    else if (d < -half) d = d + L;
+    return d;
+}
+
 // canonical squared distance of x_j relative to x_i (fold when `wrap`)
 __device__ __forceinline__ double r2_of(double xj, double yj, double zj, double xi, double yi,
                                         double zi, double L, bool wrap)
@@ -526,12 +535,18 @@ __device__ __forceinline__ double r2_of(double xj, double yj, double zj, double 
     return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
 }
 
-// candidate collection for a group ball into an LDS tile; also records
-// whether any kept candidate needed the periodic fold relative to the centre
-// and the largest per-axis displacement of a kept candidate (lane-wise, see
-// pair_wrap)
+// Candidate collection for a group ball, straight into the candidate buffer.
+// The test runs on the FP32 copies of the positions (and, for hydro, of h)
+// against the ball's squared radius widened by 2^-16 relative plus
+// 2^-18 L rad: that covers the rounding of the FP32 coordinates (at most
+// 2^-24 L each), of their differences and squares and of the radius, so
+// every particle of the exact ball is kept; the few extra ones at the rim
+// cost a filter test and change no result (the filters are exact).  Also
+// records whether a kept candidate needed the periodic fold relative to the
+// centre and the largest per-axis displacement of a kept candidate
+// (lane-wise, see pair_wrap).
 struct AppendCand {
-    const double *x, *y, *z, *h;
+    const float4 *p4; // x, y, z and, for hydro, h in FP32
     int *cand;
     int T;
     int n;
@@ -539,41 +554,47 @@ struct AppendCand {
     bool folded;
     Ball B;
     double ext;
-    __device__ bool stop() const { return over; }
-    __device__ __forceinline__ Pos fetch(int j) const
+    float cx, cy, cz, L, Rg, Hg, w2; // w2: widened density limit
+    __device__ AppendCand(const float4 *p4_, int *cand_, int T_, const Ball &B_, double ext_)
+        : p4(p4_), cand(cand_), T(T_), n(0), over(false), folded(false), B(B_), ext(ext_)
     {
-        Pos p;
-        p.x = x[j];
-        p.y = y[j];
-        p.z = z[j];
-        p.h = B.hydro ? h[j] : 0.0;
-        return p;
+        cx = (float)B.cx;
+        cy = (float)B.cy;
+        cz = (float)B.cz;
+        L = (float)B.L;
+        Rg = (float)B.Rg;
+        Hg = (float)B.Hg;
+        w2 = (float)(B.W2 * (1.0 + 0x1p-16) + 0x1p-18 * B.L * sqrt(B.W2));
     }
-    __device__ void take(int j, bool valid, const Pos &p)
+    __device__ bool stop() const { return over; }
+    __device__ __forceinline__ float4 fetch(int j) const { return p4[j]; }
+    __device__ __forceinline__ float lim(float hj) const
+    {
+        if (!B.hydro) return w2;
+        const float rad = (Rg + fmaxf(Hg, hj)) * (float)INFL;
+        return __builtin_fmaf(rad * rad, 0x1p-16f, rad * rad) + 0x1p-18f * L * rad;
+    }
+    __device__ void take(int j, bool valid, const float4 &p)
     {
         bool keep = false, fl = false;
-        double e = 0.0;
+        float e = 0.0f;
         if (B.nowrap) {
             // the ball lies inside the box: raw differences are the minimum
             // images of every candidate it can keep (and a particle whose
             // raw difference is not is farther than the ball radius either
             // way); `ext` already holds the ball radius
             if (valid) {
-                const double dx = p.x - B.cx, dy = p.y - B.cy, dz = p.z - B.cz;
-                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                const double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, p.h)) * INFL) : B.W2;
-                keep = r2 < lim;
+                const float dx = p.x - cx, dy = p.y - cy, dz = p.z - cz;
+                keep = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)) < lim(p.w);
             }
         } else if (valid) {
-            double rx = p.x - B.cx, ry = p.y - B.cy, rz = p.z - B.cz;
-            double dx = fold(rx, B.L), dy = fold(ry, B.L), dz = fold(rz, B.L);
-            double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-            double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, p.h)) * INFL) : B.W2;
-            keep = r2 < lim;
+            const float rx = p.x - cx, ry = p.y - cy, rz = p.z - cz;
+            const float dx = fold32(rx, L), dy = fold32(ry, L), dz = fold32(rz, L);
+            keep = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)) < lim(p.w);
             fl = (dx != rx) | (dy != ry) | (dz != rz);
-            e = fmax(fabs(dx), fmax(fabs(dy), fabs(dz)));
+            e = fmaxf(fabsf(dx), fmaxf(fabsf(dy), fabsf(dz)));
         }
-        if (keep) ext = fmax(ext, e);
+        if (keep) ext = fmax(ext, (double)e * (1.0 + 0x1p-20));
         const uint64_t m = ballot(keep);
         if (ballot(keep && fl)) folded = true;
         const int cnt = popc64(m);
@@ -638,8 +659,9 @@ struct WalkK {
     GroupArg ga;
     CandArg ca;
     DevStatus *st;
-    double skin; // density ball: R_g + skin * max member h
-    int hydro;   // 1: hydro ball R_g + max(max member h, h_j)
+    const float4 *pos4; // FP32 x, y, z and (hydro) h per particle
+    double skin;        // density ball: R_g + skin * max member h
+    int hydro;          // 1: hydro ball R_g + max(max member h, h_j)
 };
 
 // per-pass reset of the candidate buffer and the work counters (a kernel,
@@ -718,8 +740,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         if (!walked) { // the buffer is used up: the members walk on their own
             flags = GSUP_SOLO;
         } else {
-            AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + ck_cur, T, 0, false, false, B,
-                          nowrap ? rad : 0.0};
+            AppendCand ap(k.pos4, k.ca.cand + ck_cur, T, B, nowrap ? rad : 0.0);
             if (!walk_levels(k.g, bx.root, B, lst, lst + LCAP, lst + 2 * LCAP, ap)) // list too long: window walk
                 walk(k.g, bx.root, bx.root_end, B, ap, k.st);
             nc = uni(ap.n);
@@ -903,13 +924,6 @@ constexpr int UNR = 4; // candidate chunks loaded together
 // Pair r^2 in FP32 from the FP32 copies of the positions (rounded to
 // nearest), folded in FP32 when `wrap`.  Every path that needs a pair's FP32
 // r^2 computes it this way, so the density sums see one value per pair.
-__device__ __forceinline__ float fold32(float d, float L)
-{
-    const float half = 0.5f * L;
-    if (d >= half) d = d - L;
-    else if (d < -half) d = d + L;
-    return d;
-}
 __device__ __forceinline__ float r2_f32(float xj, float yj, float zj, float xi, float yi, float zi,
                                         float L, bool wrap)
 {
@@ -1278,7 +1292,7 @@ __device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Me
     const int wave = (int)blockIdx.x * (int)(blockDim.x >> 6) + uni((int)(threadIdx.x >> 6));
     const int64_t base = k.priv + (int64_t)wave * T;
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(rad * INFL), 0.0, 0.0, 0};
-    AppendCand ap{k.g.x, k.g.y, k.g.z, k.g.h, k.ca.cand + base, T, 0, false, false, B, 0.0};
+    AppendCand ap(k.pos4, k.ca.cand + base, T, B, 0.0);
     solo_walk(k.g, S, M, B, ap, k.st);
     ws.walks++;
     if (uni_b(ap.over)) return false;
@@ -1500,6 +1514,16 @@ __global__ void k_dens_prep(int64_t n, const double *__restrict__ x, const doubl
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], m[i]);
+}
+
+// FP32 copies of x, y, z and h (the verify pass's walk)
+__global__ void k_pos_h(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                        const double *__restrict__ z, const double *__restrict__ h,
+                        float4 *__restrict__ pos4)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], (float)h[i]);
 }
 
 __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float *__restrict__ vx,
@@ -1824,6 +1848,7 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.ga = make_groups(g, T);
     k.ca = make_cand(sb);
     k.st = st;
+    k.pos4 = sb.pos4;
     k.skin = skin;
     k.hydro = hydro;
     const size_t lds = (size_t)4 * (2 * LCAP + 64);
@@ -1933,7 +1958,11 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
 hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
                          SearchBufs &sb, const sfc_verify &v, int t_cand, DevStatus *st)
 {
-    hipError_t e = launch_walk(s, p, t, g, sb, st, t_cand, 1.0, v.mode == 1 ? 1 : 0);
+    // the walk tests FP32 copies of x, y, z and h
+    k_pos_h<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.h, sb.pos4);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_walk(s, p, t, g, sb, st, t_cand, 1.0, v.mode == 1 ? 1 : 0);
     if (e != hipSuccess) return e;
     VerK k;
     memset(&k, 0, sizeof(k));
