@@ -6,15 +6,19 @@
 //
 //  k_walk: one wavefront per group walks the octree ONCE with the group
 //    ball (centre = first member, radius = R_g + skin * max h for density,
-//    R_g + max(max h, h_j) for hydro).  The 64 lanes test 64 consecutive
-//    pre-order nodes at a time; particles of opened leaves are tested
-//    against the ball and compacted into an LDS tile in ascending order:
-//    the group's candidate superset.  The tile is copied to a global
-//    candidate buffer (bump-allocated) and a per-group record is written.
+//    R_g + max(max h, h_j) for hydro): a descent to the deepest node that
+//    holds the whole ball, then level by level over an ordered list of the
+//    reached nodes (a pre-order window walk when the list outgrows its
+//    slots).  Particles of reached leaves are tested against the ball (FP32
+//    copies, radius widened past their rounding) and written in ascending
+//    order straight into the wave's chunk of the global candidate buffer:
+//    the group's candidate superset.  A per-group record and the member ->
+//    group map are written.
 //
 //  k_density / k_hydro / k_verify: one wavefront per active particle.  The
-//    lanes hold 64 candidates of the particle's group at a time; one FP64
-//    test each gives the neighbour mask of that chunk.  Density iterates h
+//    lanes hold 64 candidates of the particle's group at a time; one test
+//    each (FP32 where provably on the same side as the FP64 test, FP64
+//    otherwise) gives the neighbour mask of that chunk.  Density iterates h
 //    on the superset while h + |x_i - x_0| stays inside the walk radius
 //    (masks of the last evaluation are kept in LDS), then streams the
 //    neighbours through an LDS FIFO in which the k-th neighbour always lands
@@ -22,9 +26,10 @@
 //    order, so the sums do not depend on the group the particle was in.
 //
 // A particle whose h outgrows the superset, and every member of a group
-// whose superset overflows the tile or the candidate buffer, finishes alone:
-// one walk per h evaluation with its own radius, neighbours streamed through
-// the same FIFO.
+// whose superset overflows the tile or the candidate buffer, takes a
+// superset of its own (density: up to three times), and else finishes
+// alone: one walk per h evaluation, neighbours streamed through the same
+// FIFO.
 //
 // Every data-dependent loop has a hard trip limit; hitting one sets
 // SFC_ST_GUARD in the status block instead of spinning.
