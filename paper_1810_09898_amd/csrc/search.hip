@@ -959,14 +959,17 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const float4 *P, cons
     const int32_t *cg = cand + M.s.c0;
     const double h2 = h * h;
     const double E = 0x1p-20 * (M.bx.L * h + h2);
-    const double lo_b = h2 - E, hi_b = h2 + E;
+    // the band's ends in FP32, rounded outwards: a candidate decided in FP32
+    // is decided as before; the few that the rounding moves into the band
+    // take the FP64 test
+    const float lo_b = __double2float_rd(h2 - E), hi_b = __double2float_ru(h2 + E);
     const float xf = (float)M.xi, yf = (float)M.yi, zf = (float)M.zi, Lf = (float)M.bx.L;
     const int cached = first ? 0 : min(nch, S.rc >> 6);
     int cnt = 0;
     for (int c = 0; c < cached; c++) {
         const int slot = (c << 6) + lane;
         const bool v = slot < nc;
-        const double r2f = v ? (double)S.r2c[slot] : 0.0;
+        const float r2f = v ? S.r2c[slot] : 0.0f;
         bool hit = r2f < lo_b;
         const bool amb = v && !hit && !(r2f > hi_b);
         if (ballot(amb)) {
@@ -1004,8 +1007,8 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const float4 *P, cons
             const int slot = ((c0 + u) << 6) + lane;
             const float r2f = r2_f32(pj[u].x, pj[u].y, pj[u].z, xf, yf, zf, Lf, wrap);
             if (first && v[u] && slot < S.rc) S.r2c[slot] = r2f;
-            bool hit = (double)r2f < lo_b;
-            const bool amb = v[u] && !hit && !((double)r2f > hi_b);
+            bool hit = r2f < lo_b;
+            const bool amb = v[u] && !hit && !(r2f > hi_b);
             if (ballot(amb)) {
                 if (amb) {
                     const int jj = j[u];
