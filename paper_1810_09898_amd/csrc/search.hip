@@ -1554,7 +1554,10 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
 
 // One wave per active particle: filter the group superset with
 // r < max(h_i, h_j), j != i, and sum the forces.
-template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro(HydroK k)
+// FP32 sums: five waves per SIMD (the register cut, a few spills, pays for
+// itself in latency hiding)
+template <int KER, typename ACC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? 5 : 1))) void k_hydro(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const MemLds S = mem_carve(lds_raw, k.ga.T, false);
