@@ -62,12 +62,10 @@ __device__ __forceinline__ double uni_d(double v)
 }
 __device__ __forceinline__ bool uni_b(bool v) { return __builtin_amdgcn_readfirstlane((int)v) != 0; }
 
-// kernel shape w(q) and w'(q), support q < 1; u = 1 - q inside the support
-// and 0 outside, which the callers form as (h - r) / h: near the edge of
-// the support h - r is exact (r and h within a factor 2), so the tail keeps
-// its relative precision where 1 - q would lose it to cancellation
-template <int KER, typename T> __device__ __forceinline__ void kern_eval(T q, T u, T &w, T &dw)
+// kernel shape w(q) and w'(q), support q < 1
+template <int KER, typename T> __device__ __forceinline__ void kern_eval(T q, T &w, T &dw)
 {
+    const T u = q < T(1) ? T(1) - q : T(0);
     if (KER == 0) {
         T wo = T(2) * u * u * u;
         T dwo = T(-6) * u * u;
@@ -1146,7 +1144,7 @@ template <int KER, typename ACC> struct DensPair {
     const float *m;
     double xi, yi, zi, L;
     bool wrap;
-    ACC hinv, hh;
+    ACC hinv;
     Kahan<ACC> sw, sd;
     struct Term {
         ACC w, d;
@@ -1160,11 +1158,9 @@ template <int KER, typename ACC> struct DensPair {
         } else {
             r2 = (ACC)e.r2;
         }
-        const ACC r = sqrt(r2);
-        ACC q = r * hinv;
-        const ACC u = r < hh ? (hh - r) * hinv : ACC(0);
+        ACC q = sqrt(r2) * hinv;
         ACC w, dw;
-        kern_eval<KER, ACC>(q, u, w, dw);
+        kern_eval<KER, ACC>(q, w, dw);
         ACC mj = (ACC)m[j];
         Term t;
         t.w = mj * w;
@@ -1193,7 +1189,6 @@ __device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, const Me
     pp.L = M.bx.L;
     pp.wrap = wrap;
     pp.hinv = (ACC)(1.0 / h);
-    pp.hh = (ACC)h;
     return pp;
 }
 
@@ -1376,7 +1371,7 @@ template <int KER, typename ACC> struct HydroPair {
     const HydroK *k;
     double xi, yi, zi, L;
     bool wrap;
-    ACC hinv, hinv4, hh, vx, vy, vz, rho, pf, cs;
+    ACC hinv, hinv4, vx, vy, vz, rho, pf, cs;
     Kahan<ACC> ax, ay, az, du;
     ACC vmax;
     struct Term {
@@ -1430,9 +1425,9 @@ template <int KER, typename ACC> struct HydroPair {
         ACC r = sqrt(r2);
         ACC rinv = r > ACC(0) ? ACC(1) / r : ACC(0);
         ACC w, dwi, dwj;
-        kern_eval<KER, ACC>(r * hinv, r < hh ? (hh - r) * hinv : ACC(0), w, dwi);
+        kern_eval<KER, ACC>(r * hinv, w, dwi);
         ACC hjinv = ACC(1) / hj;
-        kern_eval<KER, ACC>(r * hjinv, r < hj ? (hj - r) * hjinv : ACC(0), w, dwj);
+        kern_eval<KER, ACC>(r * hjinv, w, dwj);
         ACC hj2 = hjinv * hjinv;
         ACC dWi = C * dwi * hinv4;
         ACC dWj = C * dwj * (hj2 * hj2);
@@ -1475,7 +1470,6 @@ __device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, const
     hp.wrap = wrap;
     double hinv = 1.0 / M.h;
     hp.hinv = (ACC)hinv;
-    hp.hh = (ACC)M.h;
     hp.hinv4 = (ACC)(hinv * hinv * hinv * hinv);
     hp.vx = (ACC)k.vx[i];
     hp.vy = (ACC)k.vy[i];
