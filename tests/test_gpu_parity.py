@@ -450,6 +450,42 @@ def test_step_end_to_end(logn, n_leaf):
         assert np.max(np.abs(o[k][act] - ref) / A) < 2 * TOL32, k
 
 
+def test_step_batch_of_hydro_boxes():
+    """Density (h loop) then hydro over a batch of three lognormal boxes of
+    different sizes in one launch per phase, against the oracle box by box
+    (the oracle takes the same batch)."""
+    say("[step] batch of 3 lognormal boxes, density + hydro")
+    parts = [W.lognormal_hydro(n=n, grid=g, seed=sd, active=a)
+             for n, g, sd, a in ((65536, 64, 21, 0.25), (32768, 32, 22, 0.5), (49152, 32, 23, 0.3))]
+    st = {k: np.concatenate([p.state[k] for p in parts]) for k in parts[0].state}
+    sizes = [p.n for p in parts]
+    off = np.zeros(len(parts) + 1, np.int64)
+    np.cumsum(sizes, out=off[1:])
+    st["orig"] = np.arange(int(off[-1]), dtype=np.uint32)
+    w = W.Workload("hydro_batch", st, off, np.ones(len(parts)), kernel=1, n_ngb=295, dn=6,
+                   fixed_h=False, hydro=True)
+    ob, keys, perm, s, act = osorted(w)
+    r = oracle.density(s["x"], s["y"], s["z"], s["h"], s["m"], ob, act, 1, 295, 6, use_grid=True)
+    h = s["h"].copy()
+    rho = s["rho"].astype(np.float64)
+    fg = s["fgrad"].astype(np.float64)
+    h[act], rho[act], fg[act] = r.h, r.rho, r.fgrad
+    hr = oracle.hydro(s["x"], s["y"], s["z"], h, s["m"], s["vx"], s["vy"], s["vz"], s["u"], rho,
+                      fg, ob, act, 1, use_grid=True)
+    pl = Pipeline(w, StepConfig(n_leaf=64, n_group_max=24, f=0.5, t_cand=2048, hydro_t_cand=2048))
+    pl.step()
+    _sync()
+    assert pl.ctx.status()["flags"] == 0
+    sn = pl.sorted_numpy()
+    o = pl.outputs_numpy()
+    assert np.array_equal(sn["h"][act], r.h)
+    assert np.array_equal(o["nngb"][act], r.nngb)
+    assert np.max(np.abs(sn["rho"][act] / r.rho - 1)) < TOL32
+    for k, ref, A in (("ax", hr.ax, hr.abs_a), ("ay", hr.ay, hr.abs_a), ("az", hr.az, hr.abs_a),
+                      ("dudt", hr.dudt, hr.abs_du)):
+        assert np.max(np.abs(o[k][act] - ref) / A) < 2 * TOL32, k
+
+
 def test_hydro_conservation_gpu():
     """All active: total momentum and energy change vanish (pairwise
     antisymmetric terms), to FP32 rounding."""
