@@ -131,9 +131,8 @@ def run(w, cfg, label, steps, gp_box=None, graph=False, precision=False):
 def _bin_configs():
     from .pipeline import StepConfig
     # chosen by autotune.py (`--workload lognormal_bins --bins 0,1,2`)
-    return {0: StepConfig(n_leaf=64, n_group_max=36, f=0.4, t_cand=2048, hydro_t_cand=2048),
-            1: StepConfig(n_leaf=64, n_group_max=36, f=0.5, t_cand=2048, hydro_t_cand=2048),
-            2: StepConfig(n_leaf=64, n_group_max=36, f=0.5, t_cand=2048, hydro_t_cand=2048)}
+    c = StepConfig(n_leaf=128, n_group_max=36, f=0.5, t_cand=2048, hydro_t_cand=2048)
+    return {0: c, 1: c, 2: c}
 
 
 def main():
