@@ -126,6 +126,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     td.kids = b.take<int32_t>(8 * cap);
     td.lo = b.take<double4>(cap);
     td.hi = b.take<double4>(cap);
+    td.box32 = b.take<float4>(2 * cap);
     td.parent = b.take<int32_t>(cap);
     td.nchild = b.take<int32_t>(cap);
     td.counter = b.take<int32_t>(cap);

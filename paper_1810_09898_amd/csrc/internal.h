@@ -160,6 +160,8 @@ struct TreeDev {
     int32_t *kids;  // [8 * capacity]: children of a node in order, -1 past the last
     double4 *lo;    // min x, min y, min z, hmax
     double4 *hi;    // max x, max y, max z, 0
+    float4 *box32;  // [2 * capacity]: the box in FP32 rounded outwards (min down, max and
+                    // max h up): (min x, min y, min z, max h), (max x, max y, max z, 0)
     int32_t *parent;
     int32_t *nchild;
     int32_t *counter;

@@ -157,6 +157,7 @@ struct Geom {
     const double *box_L;
     const int4 *info;
     const double4 *lo, *hi;
+    const float4 *box32; // node boxes in FP32, rounded outwards
     const int32_t *kids, *nchild;
     const int32_t *box_root;
     int nb;
@@ -258,14 +259,6 @@ struct Ball {
     int nowrap;    // the ball lies inside the box: no candidate needs the periodic fold
 };
 
-__device__ __forceinline__ double axis_gap(double c, double lo, double hi, double L)
-{
-    double a = lo - c, b = c - hi;
-    double d = fmax(fmax(a, b), 0.0);
-    d = fmin(d, a + L);
-    d = fmin(d, b + L);
-    return d;
-}
 
 // position (and h) of a walked particle
 struct Pos {
@@ -346,14 +339,34 @@ __device__ __forceinline__ int wave_incl_max(int v)
 // k + 64 and the largest skip link of a closed node in the window: every
 // node in between is hidden.  Each window advances k by at least 64.
 // does the ball reach node c's bounding box (hydro: with the node's max h)?
+// In FP32 on the outward-rounded boxes, against the squared radius widened
+// by 2^-16 relative + 2^-18 L rad (the rounding of the centre, of the gaps
+// and their squares): every node the FP64 test on the exact box opens is
+// opened (a few more at the rim only cost their tests).
+__device__ __forceinline__ float axis_gap32(float c, float lo, float hi, float L)
+{
+    float a = lo - c, b = c - hi;
+    float d = fmaxf(fmaxf(a, b), 0.0f);
+    d = fminf(d, a + L);
+    d = fminf(d, b + L);
+    return d;
+}
 __device__ __forceinline__ bool node_open(const Geom &g, int c, const Ball &B)
 {
-    const double4 lo = g.lo[c], hi = g.hi[c];
-    const double gx = axis_gap(B.cx, lo.x, hi.x, B.L);
-    const double gy = axis_gap(B.cy, lo.y, hi.y, B.L);
-    const double gz = axis_gap(B.cz, lo.z, hi.z, B.L);
-    const double d2 = gx * gx + gy * gy + gz * gz;
-    const double lim = B.hydro ? sq((B.Rg + fmax(B.Hg, lo.w)) * INFL) : B.W2;
+    const float4 lo = g.box32[2 * (int64_t)c], hi = g.box32[2 * (int64_t)c + 1];
+    const float L = (float)B.L;
+    const float gx = axis_gap32((float)B.cx, lo.x, hi.x, L);
+    const float gy = axis_gap32((float)B.cy, lo.y, hi.y, L);
+    const float gz = axis_gap32((float)B.cz, lo.z, hi.z, L);
+    const float d2 = __builtin_fmaf(gz, gz, __builtin_fmaf(gy, gy, gx * gx));
+    float lim;
+    if (B.hydro) {
+        const float rad = ((float)B.Rg + fmaxf((float)B.Hg, lo.w)) * (float)INFL;
+        lim = __builtin_fmaf(rad * rad, 0x1p-16f, rad * rad) + 0x1p-18f * L * rad;
+    } else {
+        const float w2 = (float)B.W2;
+        lim = __builtin_fmaf(w2, 0x1p-16f, w2) + 0x1p-18f * L * sqrtf(w2);
+    }
     return d2 < lim;
 }
 
@@ -1781,6 +1794,7 @@ Geom make_geom(const PartDev &p, const TreeDev &t)
     g.info = t.info;
     g.lo = t.lo;
     g.hi = t.hi;
+    g.box32 = t.box32;
     g.kids = t.kids;
     g.nchild = t.nchild;
     g.box_root = t.box_root;

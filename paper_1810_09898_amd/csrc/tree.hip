@@ -223,8 +223,13 @@ __device__ __forceinline__ void box_store(const TreeDev &t, int id, const NodeBo
     if (bbox) {
         t.lo[id] = make_double4(b.lx, b.ly, b.lz, b.hm);
         t.hi[id] = make_double4(b.hx, b.hy, b.hz, 0.0);
+        t.box32[2 * (int64_t)id] = make_float4(__double2float_rd(b.lx), __double2float_rd(b.ly),
+                                               __double2float_rd(b.lz), __double2float_ru(b.hm));
+        t.box32[2 * (int64_t)id + 1] = make_float4(__double2float_ru(b.hx), __double2float_ru(b.hy),
+                                                   __double2float_ru(b.hz), 0.0f);
     } else {
         t.lo[id].w = b.hm;
+        t.box32[2 * (int64_t)id].w = __double2float_ru(b.hm);
     }
 }
 
