@@ -127,9 +127,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     td.lo = b.take<double4>(cap);
     td.hi = b.take<double4>(cap);
     td.box32 = b.take<float4>(2 * cap);
-    td.parent = b.take<int32_t>(cap);
     td.nchild = b.take<int32_t>(cap);
-    td.counter = b.take<int32_t>(cap);
     td.box_root = b.take<int32_t>(nb + 1);
     td.capacity = (int32_t)cap;
     GroupBufs gb;

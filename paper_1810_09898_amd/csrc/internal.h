@@ -162,9 +162,7 @@ struct TreeDev {
     double4 *hi;    // max x, max y, max z, 0
     float4 *box32;  // [2 * capacity]: the box in FP32 rounded outwards (min down, max and
                     // max h up): (min x, min y, min z, max h), (max x, max y, max z, 0)
-    int32_t *parent;
     int32_t *nchild;
-    int32_t *counter;
     int32_t *box_root; // [nb+1]
     int32_t capacity;
 };

@@ -84,18 +84,6 @@ __device__ __forceinline__ int64_t cell_end(const uint64_t *key, int64_t i, int6
     return bad;
 }
 
-// first index in [bs, i] whose key shares key[i]'s prefix above bit `sh`
-__device__ __forceinline__ int64_t cell_begin(const uint64_t *key, int64_t bs, int64_t i, int sh)
-{
-    uint64_t pref = key[i] >> sh;
-    int64_t lo = bs - 1, hi = i; // key[hi] matches; key[lo] differs (or lo < bs)
-    while (hi - lo > 1) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if ((key[mid] >> sh) == pref) hi = mid; else lo = mid;
-    }
-    return hi;
-}
-
 __global__ void k_tree_emit(int64_t n, int nb, const int64_t *__restrict__ box_off,
                             const uint64_t *__restrict__ key, const int8_t *__restrict__ lcp,
                             const int8_t *__restrict__ dlev, const uint32_t *__restrict__ start,
@@ -124,16 +112,6 @@ __global__ void k_tree_emit(int64_t n, int nb, const int64_t *__restrict__ box_o
         inf.z = (int)start[end];
         inf.w = l | (leaf << 8);
         t.info[id] = inf;
-        int par;
-        if (l > lo) {
-            par = (int)id - 1;
-        } else if (l == 0) {
-            par = -1;
-        } else {
-            int64_t p = cell_begin(key, bs, i, sh + 3);
-            par = (int)(start[p] + (uint32_t)((l - 1) - (lcp[p] + 1)));
-        }
-        t.parent[id] = par;
     }
 }
 
@@ -165,7 +143,6 @@ __device__ __forceinline__ void tree_children(const TreeDev &t, int id, int nn)
         }
     }
     t.nchild[id] = k;
-    t.counter[id] = 0;
     int4 *kp = (int4 *)(t.kids + 8 * (int64_t)id);
     kp[0] = make_int4(kid[0], kid[1], kid[2], kid[3]);
     kp[1] = make_int4(kid[4], kid[5], kid[6], kid[7]);
