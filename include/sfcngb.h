@@ -74,6 +74,10 @@ typedef struct {
                                   superset, in candidates per particle (0 = 96; 1..4096).
                                   Groups that do not fit finish member by member (slower,
                                   same results) and are counted in sfc_status.n_overflow. */
+    int32_t keep_supersets;    /* 1: the density and the hydro pass keep their group supersets
+                                  in buffers of their own (twice the candidate memory), so
+                                  that later calls with reuse = 1 filter them again instead
+                                  of walking; 0: one buffer, no reuse */
 } sfc_dims;
 
 /* Bytes of device workspace needed for `dims` (0 on invalid dims). */
@@ -127,6 +131,10 @@ SFC_API int tree_build(sfc_ctx *ctx, const sfc_particles *p, const uint64_t *key
 /* Recompute every node's max h from p->h (hydro_force and the hydro
  * verify pass do this themselves). */
 SFC_API int tree_refit_hmax(sfc_ctx *ctx, const sfc_particles *p);
+/* Recompute every node's bounding box and max h after the particles moved
+ * (same order, same tree structure: a node still holds the same particles,
+ * its box is whatever they now span).  Kept supersets stay kept. */
+SFC_API int tree_refit(sfc_ctx *ctx, const sfc_particles *p);
 
 /* ---------------------------------------------------------------------- */
 /* Grouping and neighbour search                                           */
@@ -195,6 +203,8 @@ typedef struct {
     int32_t accum;    /* SFC_ACCUM_* */
     double skin;      /* group walk radius = R_g + skin * max h (>= 1) */
     int32_t t_cand;   /* candidate tile (multiple of 64, <= dims.t_cand_max) */
+    int32_t reuse;    /* 1: filter the supersets kept by the last walking density call
+                         (dims.keep_supersets; same groups, same t_cand) instead of walking */
 } sfc_density_params;
 
 typedef struct {
@@ -204,6 +214,27 @@ typedef struct {
     uint8_t *converged;  /* device [n] or NULL */
     double *rho64, *drhodh64, *fgrad64; /* device [n] or NULL (written with SFC_ACCUM_F64) */
 } sfc_density_out;
+
+/* Superset reuse across steps: the Verlet-list idea that section "Neighbour
+ * Recycling in Gadget3" recalls (one superset kept over several steps),
+ * applied to the group supersets.  With
+ * dims.keep_supersets, a walking density or hydro call keeps its supersets,
+ * the group centres and radii, and a snapshot of x, y, z (density) and h
+ * (hydro).  The particles may then move and change h (keeping their order;
+ * call tree_refit), and a call with reuse = 1 skips the walks: with delta =
+ * the largest displacement since the snapshot (minimum image) and, for
+ * hydro, dh = the largest growth of any h, a member keeps its group's
+ * superset while
+ *   density: h_i + |x_i - c| + delta <= R_g + skin * max h
+ *   hydro:   h_i + |x_i - c| + delta <= R_g + (skin - 1) max h + max h  and
+ *            |x_i - c| + delta + dh <= R_g + (skin - 1) max h
+ * (c the group's centre; R_g and max h as at the walk), and otherwise
+ * finishes as a member whose h outgrew the superset.  A reuse call computes
+ * only the members whose active flag is set now, so that a finer timestep
+ * bin (a subset of the grouped particles) reuses the supersets of the step
+ * that grouped them all; an active particle outside the kept groups sets
+ * SFC_ST_REUSE_ACTIVE.  Results are those of a walking call.  sfc_sort,
+ * tree_build and group_ngb_search drop the kept supersets. */
 
 /* Density pass over the active particles of the last group_ngb_search
  * (sections "Phases of Neighbour Search" and "Adaptive Neighbour
@@ -228,6 +259,8 @@ typedef struct {
     double alpha;   /* artificial viscosity */
     int32_t accum;  /* SFC_ACCUM_* */
     int32_t t_cand; /* candidate tile */
+    double skin;    /* group walk radius = R_g + (skin - 1) * max h + max(max h, h_j), skin >= 1 */
+    int32_t reuse;  /* 1: filter the supersets kept by the last walking hydro call */
 } sfc_hydro_params;
 
 typedef struct {
@@ -251,6 +284,8 @@ SFC_API int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_pa
 #define SFC_ST_NODE_OVERFLOW 0x2u   /* octree larger than its workspace bound */
 #define SFC_ST_BAD_INPUT 0x4u       /* coordinate outside its box or h <= 0 */
 #define SFC_ST_GUARD 0x8u           /* a loop hit its trip limit (corrupt tree or h loop) */
+#define SFC_ST_REUSE_ACTIVE 0x10u   /* a reuse call found active particles outside the kept
+                                       groups (they were not computed) */
 
 typedef struct {
     uint32_t flags;          /* SFC_ST_* bits */
@@ -270,7 +305,9 @@ typedef struct {
 /* Synchronise the stream and copy the status block to *out.  Returns
  * SFC_EOVERFLOW if an overflow flag is set, SFC_OK otherwise. */
 SFC_API int sfc_status_read(sfc_ctx *ctx, sfc_status *out);
-/* Zero the device counters of the status block (enqueued; capturable). */
+/* Zero the flags and the counters of the status block (enqueued;
+ * capturable).  n_nodes, n_active and n_groups describe the current tree and
+ * grouping and are kept. */
 SFC_API int sfc_status_clear(sfc_ctx *ctx);
 
 /* Device pointers into the bound workspace (valid until re-bind). */

@@ -1,6 +1,7 @@
 // abi.hip -- the extern "C" boundary of libsfcngb: argument checks,
 // workspace layout, and the order of launches of each call.
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 
@@ -29,10 +30,12 @@ struct sfc_ctx {
     TreeBufs tb;
     TreeDev td;
     GroupBufs gb;
-    SearchBufs xb;
+    SearchBufs xb;  // the density pass (and every pass without kept supersets)
+    SearchBufs xh;  // the hydro pass: == xb unless dims.keep_supersets
     uint32_t *scan_tmp;
     int tree_leaf; // n_leaf of the last tree, 0 = none
     int have_groups;
+    int kept_d, kept_h; // t_cand of the kept density / hydro supersets, 0 = none
     bool capturing;
 };
 
@@ -93,6 +96,7 @@ bool dims_ok(const sfc_dims *d)
            d->n_boxes <= 65536 && d->n_boxes <= d->n && d->n_leaf_min >= 1 &&
            d->t_cand_max >= 64 && d->t_cand_max <= 8192 && d->t_cand_max % 64 == 0 &&
            d->cand_per_particle >= 0 && d->cand_per_particle <= 4096 &&
+           (d->keep_supersets == 0 || d->keep_supersets == 1) &&
            node_capacity(*d) < ((int64_t)1 << 31) - 1;
 }
 
@@ -149,7 +153,19 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     xb.pa = b.take<float4>(n);
     xb.pb = b.take<float4>(n);
     xb.pos4 = b.take<float4>(n);
+    xb.snap = nullptr;
+    xb.drift = nullptr;
     xb.cu_count = c ? c->cu : 0;
+    SearchBufs xh = xb;
+    if (d.keep_supersets) {
+        // the hydro pass gets buffers of its own; snapshots and drift bounds
+        xb.snap = b.take<double4>(n);
+        xb.drift = b.take<unsigned long long>(3 + 3 * 512);
+        xh.cand = b.take<int32_t>(xh.cand_cap);
+        xh.sup = b.take<GSup>(n);
+        xh.snap = b.take<double4>(n);
+        xh.drift = b.take<unsigned long long>(3 + 3 * 512);
+    }
     if (c && base) {
         c->st = st;
         c->sb = sb;
@@ -157,7 +173,9 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
         c->td = td;
         c->gb = gb;
         c->xb = xb;
+        c->xh = xh;
         c->scan_tmp = scan_tmp;
+        c->kept_d = c->kept_h = 0;
     }
     return (b.off + 255) & ~(size_t)255;
 }
@@ -269,15 +287,27 @@ int sfc_workspace_bind(sfc_ctx *ctx, const sfc_dims *dims, void *ws, size_t ws_b
     ctx->bound = true;
     ctx->tree_leaf = 0;
     ctx->have_groups = 0;
-    return sfc_status_clear(ctx);
+    ctx->kept_d = ctx->kept_h = 0;
+    // a new workspace: the whole status block, the node count included
+    hipError_t e = launch_fill_i32(ctx->stream, (int32_t *)ctx->st, 0,
+                                   (int64_t)(sizeof(DevStatus) / sizeof(int32_t)));
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "status clear");
 }
 
 int sfc_status_clear(sfc_ctx *ctx)
 {
     int r = check_ctx(ctx);
     if (r) return r;
-    hipError_t e = launch_fill_i32(ctx->stream, (int32_t *)ctx->st, 0,
-                                   (int64_t)(sizeof(DevStatus) / sizeof(int32_t)));
+    // flags and counters only: the node count of the current tree (which
+    // the refits and walks read) and the sizes of the last grouping stay
+    static_assert(offsetof(DevStatus, flags) == 0, "flags lead the status block");
+    static_assert(offsetof(DevStatus, n_deferred) % 4 == 0 && offsetof(DevStatus, cand_top) % 4 == 0,
+                  "counters are whole words");
+    int32_t *base = (int32_t *)ctx->st;
+    hipError_t e = launch_fill_i32(ctx->stream, base, 0, 1);
+    if (e == hipSuccess)
+        e = launch_fill_i32(ctx->stream, base + offsetof(DevStatus, n_deferred) / 4, 0,
+                            (int64_t)((offsetof(DevStatus, cand_top) - offsetof(DevStatus, n_deferred)) / 4));
     return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "status clear");
 }
 
@@ -301,6 +331,7 @@ int sfc_sort(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out, uint64_t
     if (e != hipSuccess) return hip_fail(ctx, e, "gather");
     ctx->tree_leaf = 0;
     ctx->have_groups = 0;
+    ctx->kept_d = ctx->kept_h = 0;
     return SFC_OK;
 }
 
@@ -319,6 +350,7 @@ int tree_build(sfc_ctx *ctx, const sfc_particles *p, const uint64_t *keys, int32
     if (e != hipSuccess) return hip_fail(ctx, e, "tree_build");
     ctx->tree_leaf = n_leaf;
     ctx->have_groups = 0;
+    ctx->kept_d = ctx->kept_h = 0;
     return SFC_OK;
 }
 
@@ -331,6 +363,17 @@ int tree_refit_hmax(sfc_ctx *ctx, const sfc_particles *p)
     PartDev pd = part_dev(p);
     hipError_t e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
     return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "tree_refit_hmax");
+}
+
+int tree_refit(sfc_ctx *ctx, const sfc_particles *p)
+{
+    int r = check_ctx(ctx);
+    if (r) return r;
+    if ((r = check_particles(ctx, p, false))) return r;
+    if (!ctx->tree_leaf) return fail(ctx, SFC_EORDER, "tree_refit: no tree");
+    PartDev pd = part_dev(p);
+    hipError_t e = launch_tree_refit(ctx->stream, pd, ctx->td, true, ctx->st, p->n);
+    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "tree_refit");
 }
 
 static int check_group_params(sfc_ctx *ctx, const sfc_group_params *gp)
@@ -378,6 +421,7 @@ int group_ngb_search(sfc_ctx *ctx, const sfc_particles *p, const sfc_group_param
                                  ctx->gb, ctx->scan_tmp, ctx->st);
     if (e != hipSuccess) return hip_fail(ctx, e, "groups");
     ctx->have_groups = 1;
+    ctx->kept_d = ctx->kept_h = 0;
     if (verify) {
         if (verify->mode == 1) {
             e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
@@ -405,13 +449,22 @@ int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp, sfc_de
     if (dp->accum != SFC_ACCUM_F32 && dp->accum != SFC_ACCUM_F64)
         return fail(ctx, SFC_EINVAL, "density: bad accum");
     if ((r = check_tile(ctx, dp->t_cand))) return r;
+    if (dp->reuse != 0 && dp->reuse != 1) return fail(ctx, SFC_EINVAL, "density: reuse must be 0 or 1");
+    if (dp->reuse && ctx->kept_d == 0)
+        return fail(ctx, SFC_EORDER, "density: reuse without kept supersets (dims.keep_supersets, "
+                                     "a walking density call since group_ngb_search)");
+    if (dp->reuse && ctx->kept_d != dp->t_cand)
+        return fail(ctx, SFC_EINVAL, "density: reuse needs the kept t_cand %d", ctx->kept_d);
     DensityArgs a;
     a.dp = *dp;
+    a.keep = ctx->dims.keep_supersets && !dp->reuse;
     if (out) a.out = *out;
     else memset(&a.out, 0, sizeof(a.out));
     PartDev pd = part_dev(p);
     hipError_t e = launch_density(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
-    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "density");
+    if (e != hipSuccess) return hip_fail(ctx, e, "density");
+    if (a.keep) ctx->kept_d = dp->t_cand;
+    return SFC_OK;
 }
 
 int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp,
@@ -433,15 +486,27 @@ int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp
     if (hp->accum != SFC_ACCUM_F32 && hp->accum != SFC_ACCUM_F64)
         return fail(ctx, SFC_EINVAL, "hydro_force: bad accum");
     if ((r = check_tile(ctx, hp->t_cand))) return r;
+    if (!(hp->skin >= 1.0 && hp->skin <= 4.0))
+        return fail(ctx, SFC_EINVAL, "hydro_force: skin must be in [1, 4]");
+    if (hp->reuse != 0 && hp->reuse != 1)
+        return fail(ctx, SFC_EINVAL, "hydro_force: reuse must be 0 or 1");
+    if (hp->reuse && ctx->kept_h == 0)
+        return fail(ctx, SFC_EORDER, "hydro_force: reuse without kept supersets");
+    if (hp->reuse && ctx->kept_h != hp->t_cand)
+        return fail(ctx, SFC_EINVAL, "hydro_force: reuse needs the kept t_cand %d", ctx->kept_h);
     HydroArgs a;
     a.hp = *hp;
     a.out = *out;
+    a.keep = ctx->dims.keep_supersets && !hp->reuse;
     PartDev pd = part_dev(p);
-    // the hydro walk reads every node's max h: refresh it from the current h
-    hipError_t e = launch_tree_refit(ctx->stream, pd, ctx->td, false, ctx->st, p->n);
+    // the hydro walks read every node's max h: refresh it from the current h
+    // (and the boxes after a drift, for the members that walk alone)
+    hipError_t e = launch_tree_refit(ctx->stream, pd, ctx->td, hp->reuse != 0, ctx->st, p->n);
     if (e != hipSuccess) return hip_fail(ctx, e, "hydro_force refit");
-    e = launch_hydro(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
-    return e == hipSuccess ? SFC_OK : hip_fail(ctx, e, "hydro_force");
+    e = launch_hydro(ctx->stream, pd, ctx->td, ctx->gb, ctx->xh, a, ctx->st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hydro_force");
+    if (a.keep) ctx->kept_h = hp->t_cand;
+    return SFC_OK;
 }
 
 int sfc_status_read(sfc_ctx *ctx, sfc_status *out)

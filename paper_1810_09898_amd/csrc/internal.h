@@ -134,7 +134,7 @@ struct DevStatus {
     unsigned long long sum_iters;
     unsigned long long sum_tests;
     unsigned long long sum_pairs;
-    int32_t pad[2];
+    unsigned long long pass_members; // members computed by the last reuse pass
     // Per-pass counters of the search kernels, one per eighth of the work
     // items, each on its own 128-byte line so that the eighths do not
     // serialise on one address: bump pointers of the eight regions of the
@@ -146,9 +146,11 @@ struct DevStatus {
 // per-group record written by the walk kernel
 #define GSUP_WRAP 1 // pairs of this group need the periodic fold
 #define GSUP_SOLO 2 // superset not kept (tile or buffer overflow): members walk alone
+#define GSUP_FRESH 4 // a member's own superset, walked at the current positions
 struct GSup {
     double cx, cy, cz; // centre: the group's first member
-    double cov;        // walk radius (density: R_g + skin * max member h)
+    double cov;        // walk radius (density: R_g + skin * max member h; hydro: rs + max h)
+    double rs;         // hydro: R_g + (skin - 1) * max member h
     int64_t c0;        // first candidate in the candidate buffer
     int32_t nc;        // number of candidates
     int32_t flags;
@@ -253,15 +255,20 @@ struct SearchBufs {
     int32_t *grp;     // [n] per active: its group
     float4 *pa, *pb;  // [n] hydro records: (m, v) and (rho, f P / rho^2, c, h)
     float4 *pos4;     // [n] density: FP32 x, y, z and m
+    double4 *snap;    // [n] kept supersets: x, y, z (and h) when they were walked, or NULL
+    unsigned long long *drift; // [3 + 3 * 512] largest displacement, largest h growth since
+                               // (FP64 bits), active particles now; per-block partials
     int32_t cu_count;
 };
 struct DensityArgs {
     sfc_density_params dp;
     sfc_density_out out;
+    bool keep; // snapshot x, y, z for a later reuse
 };
 struct HydroArgs {
     sfc_hydro_params hp;
     sfc_hydro_out out;
+    bool keep; // snapshot x, y, z, h for a later reuse
 };
 hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
                           SearchBufs &sb, const DensityArgs &a, DevStatus *st);

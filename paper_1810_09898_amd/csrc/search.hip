@@ -131,7 +131,7 @@ __device__ __forceinline__ unsigned long long uni_u64(unsigned long long v)
 // leaves: a status counter updated by every particle or group would
 // serialise the whole grid on one address.
 struct WaveStats {
-    uint32_t walks = 0, overflow = 0, deferred = 0, iters = 0, not_conv = 0;
+    uint32_t walks = 0, overflow = 0, deferred = 0, iters = 0, not_conv = 0, members = 0;
     unsigned long long cand = 0, tests = 0, pairs = 0;
     __device__ __forceinline__ void flush(DevStatus *st) const
     {
@@ -144,6 +144,7 @@ struct WaveStats {
         if (not_conv) atomicAdd(&st->n_not_converged, (unsigned long long)not_conv);
         if (tests) atomicAdd(&st->sum_tests, tests);
         if (pairs) atomicAdd(&st->sum_pairs, pairs);
+        if (members) atomicAdd(&st->pass_members, (unsigned long long)members);
     }
 };
 
@@ -676,8 +677,8 @@ struct WalkK {
     CandArg ca;
     DevStatus *st;
     const float4 *pos4; // FP32 x, y, z and (hydro) h per particle
-    double skin;        // density ball: R_g + skin * max member h
-    int hydro;          // 1: hydro ball R_g + max(max member h, h_j)
+    double skin;        // density ball: R_g + skin * max h; hydro: R_g + (skin - 1) * max h
+    int hydro;          // 1: hydro ball R_s + max(max member h, h_j), R_s = R_g + (skin - 1) max h
 };
 
 // per-pass reset of the candidate buffer and the work counters (a kernel,
@@ -690,6 +691,14 @@ __global__ void k_reset_pass(DevStatus *st)
         st->cand_top[16 * t] = 0ull;
         st->qctr[32 * t] = 0;
     }
+    if (t == 8) st->pass_members = 0ull;
+}
+
+// After a reuse pass: every particle active now was a member of a kept group
+__global__ void k_reuse_check(const unsigned long long *drift, DevStatus *st)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0 && st->pass_members != drift[2])
+        atomicOr(&st->flags, (unsigned)SFC_ST_REUSE_ACTIVE);
 }
 
 // One wave per group: the walk, the superset straight into the global
@@ -732,14 +741,17 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         const double d = mem ? sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx))) : 0.0;
         const double R = uni_d(wave_max_d(d));
         const double H = uni_d(wave_max_d(hi));
-        const double cov = k.hydro ? R + H : R + k.skin * H;
+        // hydro: the group radius widened by the skin (kept supersets stay
+        // valid while members and neighbours move and h grows within it)
+        const double Rs = k.hydro ? R + (k.skin - 1.0) * H : R;
+        const double cov = k.hydro ? Rs + H : R + k.skin * H;
         // largest distance a kept candidate can have; the ball needs no
         // periodic fold when it stays inside the box on every axis
         const double rad =
-            (k.hydro ? (R + fmax(H, uni_d(k.g.lo[bx.root].w))) * INFL : cov * INFL) * (1.0 + 0x1p-20);
+            (k.hydro ? (Rs + fmax(H, uni_d(k.g.lo[bx.root].w))) * INFL : cov * INFL) * (1.0 + 0x1p-20);
         const int nowrap = cx - rad >= 0.0 && cx + rad < bx.L && cy - rad >= 0.0 &&
                            cy + rad < bx.L && cz - rad >= 0.0 && cz + rad < bx.L;
-        Ball B{cx, cy, cz, bx.L, sq(cov * INFL), R, H, k.hydro, nowrap};
+        Ball B{cx, cy, cz, bx.L, sq(cov * INFL), Rs, H, k.hydro, nowrap};
         // the superset goes straight to the wave's current chunk of the
         // buffer, which must hold a full tile (a new chunk otherwise; the
         // rest of the old one stays unused)
@@ -774,6 +786,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
             sp.cy = cy;
             sp.cz = cz;
             sp.cov = cov;
+            sp.rs = Rs;
             sp.c0 = c0;
             sp.nc = (flags & GSUP_SOLO) ? 0 : nc;
             sp.flags = flags;
@@ -840,6 +853,7 @@ __device__ __forceinline__ Member member(const Geom &geo, const GroupArg &ga, co
     M.s.cy = uni_d(sp->cy);
     M.s.cz = uni_d(sp->cz);
     M.s.cov = uni_d(sp->cov);
+    M.s.rs = uni_d(sp->rs);
     const int64_t c0 = sp->c0;
     M.s.c0 = ((int64_t)uni((int)(c0 >> 32)) << 32) | (uint32_t)uni((int)(uint32_t)c0);
     M.s.nc = uni(sp->nc);
@@ -1147,6 +1161,8 @@ struct DensK {
     sfc_density_out out;
     DevStatus *st;
     int64_t priv; // offset in the candidate buffer of the private slots (T per wave), -1: none
+    const unsigned long long *drift; // reused supersets: [0] largest displacement (FP64 bits), or NULL
+    const uint8_t *active;           // reused supersets: members computed now, or NULL
     int n_ngb, dn, max_iter, fixed_h;
 };
 
@@ -1273,12 +1289,14 @@ namespace {
 // the masks of the last evaluation stay in LDS
 __device__ __forceinline__ int iterate(const DensK &k, const Member &M, const MemLds &S, double &h,
                                        double &lo, double &hi, int &it, int &nn, bool &conv,
-                                       WaveStats &ws)
+                                       double dl, WaveStats &ws)
 {
-    const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
+    // a reused superset: every particle may have moved by dl since the walk
+    const double d = (M.s.flags & GSUP_FRESH) ? M.d : M.d + dl;
+    const bool wrap = (M.s.flags & GSUP_WRAP) != 0 || k.drift != nullptr;
     bool first = true;
     while (it < k.max_iter) {
-        if (!(h + M.d <= M.s.cov)) return 0;
+        if (!(h + d <= M.s.cov)) return 0;
         nn = count_pass(k.g, k.pos4, k.ca.cand, M, h, wrap, S, first);
         ws.tests += (unsigned)M.s.nc;
         first = false;
@@ -1318,7 +1336,7 @@ __device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Me
     M.s.cov = rad;
     M.s.c0 = (int64_t)base;
     M.s.nc = uni(ap.n);
-    M.s.flags = GSUP_WRAP;
+    M.s.flags = GSUP_WRAP | GSUP_FRESH;
     M.d = 0.0;
     return true;
 }
@@ -1336,14 +1354,19 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
     const int A = uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
     WaveStats ws;
+    const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
     for (int a = ar.i; a < ar.end; a += ar.stride) {
+        if (k.active) { // reuse: the members active now
+            if (!k.active[uni(k.ga.act[a])]) continue;
+            ws.members++;
+        }
         Member M = member(k.g, k.ga, k.ca, a);
         double h = M.h, lo = 0.0, hi = INFINITY;
         int it = 0, nn = 0;
         bool conv = false, done = false;
         bool usable = (M.s.flags & GSUP_SOLO) == 0;
         for (int round = 0; round < 4; round++) {
-            if (usable && iterate(k, M, S, h, lo, hi, it, nn, conv, ws)) {
+            if (usable && iterate(k, M, S, h, lo, hi, it, nn, conv, dl, ws)) {
                 done = true;
                 break;
             }
@@ -1357,9 +1380,10 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
             dens_solo<KER, ACC>(k, S, M, h, lo, hi, it, ws);
             continue;
         }
-        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, (M.s.flags & GSUP_WRAP) != 0);
+        const bool wrap = (M.s.flags & GSUP_WRAP) != 0 || k.drift != nullptr;
+        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, wrap);
         Fifo q{(DEnt *)S.fifo, 0};
-        stream_masks(k.pos4, k.ca.cand, M, S, (M.s.flags & GSUP_WRAP) != 0, q, pp);
+        stream_masks(k.pos4, k.ca.cand, M, S, wrap, q, pp);
         dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
     }
     ws.flush(k.st);
@@ -1374,6 +1398,8 @@ struct HydroK {
     const float4 *pa;   // per particle: m, vx, vy, vz
     const float4 *pb;   // per particle: rho, f P / rho^2, sound speed, h
     const float4 *pos4; // per particle: FP32 x, y, z, h
+    const unsigned long long *drift; // reused supersets: largest displacement, h growth, or NULL
+    const uint8_t *active;           // reused supersets: members computed now, or NULL
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
@@ -1524,11 +1550,78 @@ __device__ void hydro_write(const HydroK &k, int i, const HydroPair<KER, ACC> &h
 
 __global__ void k_dens_prep(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                             const double *__restrict__ z, const float *__restrict__ m,
-                            float4 *__restrict__ pos4)
+                            float4 *__restrict__ pos4, double4 *__restrict__ snap)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], m[i]);
+    if (snap) snap[i] = make_double4(x[i], y[i], z[i], 0.0);
+}
+
+// Drift since the snapshot of kept supersets: the largest displacement
+// (minimum image in its box) and the largest growth of h, as the bit
+// patterns of non-negative doubles (whose order is the numbers' order), and
+// the number of active particles.  First per block into part[3 * block],
+// then k_drift_final.
+constexpr int DRIFT_BLOCKS = 512;
+__global__ __launch_bounds__(256) void k_drift_part(int64_t n, int nb, const int64_t *__restrict__ box_off,
+                                                    const double *__restrict__ box_L,
+                                                    const double *__restrict__ x, const double *__restrict__ y,
+                                                    const double *__restrict__ z, const double *__restrict__ h,
+                                                    const uint8_t *__restrict__ active,
+                                                    const double4 *__restrict__ snap,
+                                                    unsigned long long *__restrict__ part)
+{
+    __shared__ unsigned long long red[3][256];
+    unsigned long long dm = 0, hm = 0, na = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double L = box_L[nb > 1 ? box_of(box_off, nb, (int)i) : 0];
+        const double4 s = snap[i];
+        const double dx = fold(x[i] - s.x, L), dy = fold(y[i] - s.y, L), dz = fold(z[i] - s.z, L);
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        dm = max(dm, (unsigned long long)__double_as_longlong(d));
+        if (h) hm = max(hm, (unsigned long long)__double_as_longlong(fmax(h[i] - s.w, 0.0)));
+        na += active[i] != 0;
+    }
+    red[0][threadIdx.x] = dm;
+    red[1][threadIdx.x] = hm;
+    red[2][threadIdx.x] = na;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] = max(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+            red[2][threadIdx.x] += red[2][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_drift_final(const unsigned long long *__restrict__ part,
+                                                     unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long red[3][256];
+    unsigned long long dm = 0, hm = 0, na = 0;
+    for (int b = threadIdx.x; b < DRIFT_BLOCKS; b += 256) {
+        dm = max(dm, part[3 * b]);
+        hm = max(hm, part[3 * b + 1]);
+        na += part[3 * b + 2];
+    }
+    red[0][threadIdx.x] = dm;
+    red[1][threadIdx.x] = hm;
+    red[2][threadIdx.x] = na;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] = max(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+            red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+            red[2][threadIdx.x] += red[2][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 // FP32 copies of x, y, z and h (the verify pass's walk)
@@ -1547,10 +1640,12 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
                              const float *__restrict__ u, const double *__restrict__ h,
                              const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ z, double gamma, float4 *__restrict__ pa,
-                             float4 *__restrict__ pb, float4 *__restrict__ pos4)
+                             float4 *__restrict__ pb, float4 *__restrict__ pos4,
+                             double4 *__restrict__ snap)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (snap) snap[i] = make_double4(x[i], y[i], z[i], h[i]);
     double gm1 = gamma - 1.0;
     double uu = u[i];
     pa[i] = make_float4(m[i], vx[i], vy[i], vz[i]);
@@ -1572,9 +1667,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
     const int A = uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
     WaveStats ws;
+    // reused supersets: the largest displacement and h growth since the walk
+    const double dl = k.drift ? __longlong_as_double((long long)k.drift[0]) : 0.0;
+    const double dh = k.drift ? __longlong_as_double((long long)k.drift[1]) : 0.0;
     for (int a = ar.i; a < ar.end; a += ar.stride) {
+        if (k.active) { // reuse: the members active now
+            if (!k.active[uni(k.ga.act[a])]) continue;
+            ws.members++;
+        }
         const Member M = member(k.g, k.ga, k.ca, a);
-        if (M.s.flags & GSUP_SOLO) {
+        const bool kept = !k.drift || (M.h + M.d + dl <= M.s.cov && M.d + dl + dh <= M.s.rs);
+        if ((M.s.flags & GSUP_SOLO) || !kept) {
             ws.deferred++;
             HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
             StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
@@ -1586,7 +1689,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
             hydro_write<KER, ACC>(k, M.i, hp);
             continue;
         }
-        const bool wrap = (M.s.flags & GSUP_WRAP) != 0;
+        const bool wrap = (M.s.flags & GSUP_WRAP) != 0 || k.drift != nullptr;
         HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, wrap);
         FifoH q{(HEnt *)S.fifo, 0};
         // the filter decides r < max(h_i, h_j) on FP32 positions and h (as
@@ -1873,6 +1976,18 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     const size_t lds = (size_t)4 * (2 * LCAP + 64);
     return launch_persistent(k_walk, s, k, 64, lds, sb.cu_count, p.n);
 }
+
+// the drift bounds of kept supersets and the active count into
+// sb.drift[0..2] (h: NULL for none)
+hipError_t launch_drift(hipStream_t s, const PartDev &p, const double *h, const SearchBufs &sb)
+{
+    k_drift_part<<<DRIFT_BLOCKS, 256, 0, s>>>(p.n, p.nb, p.box_off, p.box_L, p.x, p.y, p.z, h,
+                                              p.active, sb.snap, sb.drift + 3);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_drift_final<<<1, 256, 0, s>>>(sb.drift + 3, sb.drift);
+    return hipGetLastError();
+}
 } // namespace
 
 namespace {
@@ -1897,10 +2012,17 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     const int64_t priv = (int64_t)grid * MEM_WAVES * dp.t_cand;
     SearchBufs gs = sb;
     if (priv <= sb.cand_cap / 2) gs.cand_cap = sb.cand_cap - priv;
-    k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.m, sb.pos4);
+    k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.m, sb.pos4,
+                                                              a.keep ? sb.snap : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_walk(s, p, t, g, gs, st, dp.t_cand, dp.skin, 0);
+    if (dp.reuse) {
+        // the kept supersets: the walk is skipped, the drift bounds them
+        k_reset_pass<<<1, 64, 0, s>>>(st);
+        e = launch_drift(s, p, nullptr, sb);
+    } else {
+        e = launch_walk(s, p, t, g, gs, st, dp.t_cand, dp.skin, 0);
+    }
     if (e != hipSuccess) return e;
     DensK k;
     memset(&k, 0, sizeof(k));
@@ -1918,7 +2040,12 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.dn = dp.dn;
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
+    k.drift = dp.reuse ? sb.drift : nullptr;
+    k.active = dp.reuse ? p.active : nullptr;
     kern<<<grid, th, lds, s>>>(k);
+    e = hipGetLastError();
+    if (e != hipSuccess || !dp.reuse) return e;
+    k_reuse_check<<<1, 64, 0, s>>>(sb.drift, st);
     return hipGetLastError();
 }
 } // namespace
@@ -1939,10 +2066,16 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     const sfc_hydro_params &hp = a.hp;
     k_hydro_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.m, p.vx, p.vy, p.vz, p.rho,
                                                                p.fgrad, p.u, p.h, p.x, p.y, p.z,
-                                                               hp.gamma, sb.pa, sb.pb, sb.pos4);
+                                                               hp.gamma, sb.pa, sb.pb, sb.pos4,
+                                                               a.keep ? sb.snap : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_walk(s, p, t, g, sb, st, hp.t_cand, 1.0, 1);
+    if (hp.reuse) {
+        k_reset_pass<<<1, 64, 0, s>>>(st);
+        e = launch_drift(s, p, p.h, sb);
+    } else {
+        e = launch_walk(s, p, t, g, sb, st, hp.t_cand, hp.skin, 1);
+    }
     if (e != hipSuccess) return e;
     HydroK k;
     memset(&k, 0, sizeof(k));
@@ -1963,15 +2096,22 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
+    k.drift = hp.reuse ? sb.drift : nullptr;
+    k.active = hp.reuse ? p.active : nullptr;
     const size_t lds = MEM_WAVES * mem_lds_bytes(hp.t_cand, false);
     const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;
     if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32)
-        return launch_persistent(k_hydro<0, float>, s, k, th, lds, sb.cu_count, n);
-    if (hp.kernel == 0) return launch_persistent(k_hydro<0, double>, s, k, th, lds, sb.cu_count, n);
-    if (hp.accum == SFC_ACCUM_F32)
-        return launch_persistent(k_hydro<1, float>, s, k, th, lds, sb.cu_count, n);
-    return launch_persistent(k_hydro<1, double>, s, k, th, lds, sb.cu_count, n);
+        e = launch_persistent(k_hydro<0, float>, s, k, th, lds, sb.cu_count, n);
+    else if (hp.kernel == 0)
+        e = launch_persistent(k_hydro<0, double>, s, k, th, lds, sb.cu_count, n);
+    else if (hp.accum == SFC_ACCUM_F32)
+        e = launch_persistent(k_hydro<1, float>, s, k, th, lds, sb.cu_count, n);
+    else
+        e = launch_persistent(k_hydro<1, double>, s, k, th, lds, sb.cu_count, n);
+    if (e != hipSuccess || !hp.reuse) return e;
+    k_reuse_check<<<1, 64, 0, s>>>(sb.drift, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_verify(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,

@@ -13,6 +13,12 @@ density + hydro, and the status counters of one step.
   a HIP graph and replayed, and the FP32-compensated results compared with
   the FP64-accumulator variant on the GPU (relative errors per field).
 - the other workloads: one line.
+- --reuse SKINS: superset reuse after a drift.  Per skin, a walking step that
+  keeps its supersets, then per drift (the fastest particle moving FRACS times
+  the smallest h, as in a global step limited by the Courant condition;
+  positions advanced in place along v) the step on the kept
+  supersets (tree refit, density, hydro; h reset to the walking step's input
+  before each repetition), beside the ordinary step (skin 1, nothing kept).
 """
 from __future__ import annotations
 
@@ -128,6 +134,75 @@ def run(w, cfg, label, steps, gp_box=None, graph=False, precision=False):
     return line
 
 
+def _reuse_phases(pl, h0, reps):
+    import torch
+    names = ["refit", "density", "hydro"]
+    calls = [pl.refit, lambda: pl.density(reuse=True), lambda: pl.hydro_force(reuse=True)]
+    out = {k: [] for k in names}
+    st = pl.ctx.stream
+    for _ in range(reps):
+        with torch.cuda.stream(st):
+            pl.ps.t["h"].copy_(h0)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in names]
+        for (a, b), f in zip(ev, calls):
+            a.record(st)
+            f()
+            b.record(st)
+        torch.cuda.synchronize()
+        for k, (a, b) in zip(names, ev):
+            out[k].append(a.elapsed_time(b))
+    return {k: float(np.median(v)) for k, v in out.items()}
+
+
+def reuse_scan(w, cfg, steps, skins, fracs):
+    import torch
+    from .pipeline import Pipeline
+    A = int(w.state["active"].sum())
+    base = Pipeline(w, cfg)
+    base.step()
+    ph = _phases(base, steps)
+    t_base = sum(ph.values())
+    del base
+    print(json.dumps({"workload": w.name, "kind": "ordinary step", "phases_ms": ph,
+                      "step_ms": round(t_base, 4)}), flush=True)
+    for skin in skins:
+        # a skin makes the supersets larger: a larger tile keeps them whole
+        T = cfg.t_cand if skin == 1.0 else 2 * cfg.t_cand
+        c = cfg.with_(skin=skin, hydro_skin=skin, keep_supersets=True, t_cand=T, hydro_t_cand=T)
+        pl = Pipeline(w, c)
+        pl.step()
+        torch.cuda.synchronize()
+        ph_keep = _phases(pl, steps)  # walking steps that keep (the last one stays kept)
+        t = pl.ps.t
+        x0, y0, z0, h0 = (t[k].clone() for k in ("x", "y", "z", "h"))
+        L = torch.as_tensor(w.box_L, dtype=torch.float64, device="cuda")
+        Lp = L[0] if len(w.box_L) == 1 else None
+        v = torch.sqrt(t["vx"].double() ** 2 + t["vy"].double() ** 2 + t["vz"].double() ** 2)
+        hmin = float(torch.min(h0))
+        for frac in fracs:
+            dt = frac * hmin / float(v.max())
+            for k, k0, vk in (("x", x0, "vx"), ("y", y0, "vy"), ("z", z0, "vz")):
+                a = torch.remainder(k0 + dt * t[vk].double(), Lp)
+                t[k].copy_(torch.where(a >= Lp, a - Lp, a))
+            pl.ctx.status_clear()
+            t["h"].copy_(h0)
+            pl.reuse_step()
+            torch.cuda.synchronize()
+            st = pl.ctx.status(raise_on_overflow=False)
+            ph_r = _reuse_phases(pl, h0, steps)
+            tr = sum(ph_r.values())
+            print(json.dumps({
+                "workload": w.name, "kind": "reuse", "skin": skin, "drift_frac_min_h": frac,
+                "walking_keep_step_ms": round(sum(ph_keep.values()), 4),
+                "walking_keep_phases_ms": ph_keep, "reuse_step_ms": round(tr, 4),
+                "reuse_phases_ms": ph_r, "ordinary_step_ms": round(t_base, 4),
+                "reuse_updates_per_s": round(A / (tr * 1e-3), 1),
+                "deferred_frac": round(st["n_deferred"] / max(A, 1) / 2, 5),
+                "status": st}), flush=True)
+        del pl
+
+
 def _bin_configs():
     from .pipeline import StepConfig
     # chosen by autotune.py (`--workload lognormal_bins --bins 0,1,2`)
@@ -139,6 +214,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="lognormal_hydro")
     ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--reuse", default="", help="comma-separated skins: superset reuse scan")
+    ap.add_argument("--fracs", default="0.05,0.1,0.3")
     args = ap.parse_args()
     from . import workloads as W
     from . import autotune
@@ -150,7 +227,11 @@ def main():
     w = W.WORKLOADS[args.workload]()
     print(f"# {args.workload}: generated in {time.time() - t0:.1f} s, n={w.n}", file=sys.stderr,
           flush=True)
-    if args.workload == "plummer_batch":
+    if args.reuse:
+        cfg = StepConfig(n_leaf=128, n_group_max=24, f=0.5, t_cand=2048, hydro_t_cand=2048)
+        reuse_scan(w, cfg, args.steps, [float(v) for v in args.reuse.split(",")],
+                   [float(v) for v in args.fracs.split(",")])
+    elif args.workload == "plummer_batch":
         cfg = StepConfig(n_leaf=16, n_group_max=32, f=0.5, t_cand=1024, hydro_t_cand=1024)
         run(w, cfg, "plummer_batch (per-box parameters)", args.steps,
             gp_box=autotune.per_box_params(w, autotune.batch_rule))

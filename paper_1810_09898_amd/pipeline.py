@@ -29,6 +29,8 @@ class StepConfig:
     t_cand: int = 2048
     hydro_t_cand: int = 2048
     skin: float = 1.0
+    hydro_skin: float = 1.0
+    keep_supersets: bool = False  # keep the supersets for reuse after a drift
     accum: int = S.ACCUM_F32
     max_iter: int = 64
     gamma: float = 5.0 / 3.0
@@ -61,7 +63,8 @@ class Pipeline:
         t_max = max(cfg.t_cand, cfg.hydro_t_cand)
         t_max = max(64, ((t_max + 63) // 64) * 64)
         self.ctx = S.Context(n, len(w.box_L), n_leaf_min=min(cfg.n_leaf, 8), t_cand_max=t_max,
-                             cand_per_particle=cand_per_particle)
+                             cand_per_particle=cand_per_particle,
+                             keep_supersets=cfg.keep_supersets)
         f32 = lambda: torch.zeros(n, dtype=torch.float32, device=dev)  # noqa: E731
         f64 = lambda: torch.zeros(n, dtype=torch.float64, device=dev)  # noqa: E731
         i32 = lambda: torch.zeros(n, dtype=torch.int32, device=dev)  # noqa: E731
@@ -84,7 +87,8 @@ class Pipeline:
         self.dout = S.DensityOut(p("drhodh"), p("nngb"), p("iters"), p("converged"),
                                  p("rho64"), p("drhodh64"), p("fgrad64"))
         if self.hydro:
-            self.hp = S.HydroParams(w.kernel, cfg.gamma, cfg.alpha, cfg.accum, cfg.hydro_t_cand)
+            self.hp = S.HydroParams(w.kernel, cfg.gamma, cfg.alpha, cfg.accum, cfg.hydro_t_cand,
+                                    cfg.hydro_skin)
             self.hout = S.HydroOut(p("ax"), p("ay"), p("az"), p("dudt"), p("vsigmax"),
                                    p("ax64"), p("ay64"), p("az64"), p("dudt64"))
 
@@ -101,11 +105,25 @@ class Pipeline:
                                   gp_box=self.gp_box, verify=verify,
                                   t_cand=t_cand or c.t_cand, level=c.level)
 
-    def density(self):
+    def density(self, reuse=False):
+        self.dp.reuse = int(reuse)
         self.ctx.density(self.ps, self.dp, self.dout)
 
-    def hydro_force(self):
+    def hydro_force(self, reuse=False):
+        self.hp.reuse = int(reuse)
         self.ctx.hydro_force(self.ps, self.hp, self.hout)
+
+    def refit(self):
+        """Node boxes and max h after the sorted particles moved in place."""
+        self.ctx.tree_refit(self.ps)
+
+    def reuse_step(self):
+        """After the sorted particles moved: the step on the kept supersets
+        (needs keep_supersets and a walking step since the last regrouping)."""
+        self.refit()
+        self.density(reuse=True)
+        if self.hydro:
+            self.hydro_force(reuse=True)
 
     def step(self):
         self.sort()

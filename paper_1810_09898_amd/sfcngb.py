@@ -20,12 +20,12 @@ SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_EHIP, SFC_EOVERFLOW, SFC_EORDER = 0, -1,
 POLICY_COUNT, POLICY_PAPER, POLICY_TREE = 0, 1, 2
 KERNEL_CUBIC, KERNEL_WC6 = 0, 1
 ACCUM_F32, ACCUM_F64 = 0, 1
-ST_LIST_OVERFLOW, ST_NODE_OVERFLOW, ST_BAD_INPUT = 1, 2, 4
+ST_LIST_OVERFLOW, ST_NODE_OVERFLOW, ST_BAD_INPUT, ST_GUARD, ST_REUSE_ACTIVE = 1, 2, 4, 8, 16
 
 EXPORTS = [
     "sfc_ctx_create", "sfc_ctx_destroy", "sfc_ctx_set_stream", "sfc_ctx_last_error",
     "sfc_ctx_cu_count", "sfc_workspace_bytes", "sfc_workspace_bind", "sfc_sort", "tree_build",
-    "tree_refit_hmax", "group_ngb_search", "density", "hydro_force", "sfc_status_read",
+    "tree_refit_hmax", "tree_refit", "group_ngb_search", "density", "hydro_force", "sfc_status_read",
     "sfc_status_clear", "sfc_get_views", "sfc_graph_begin", "sfc_graph_end",
     "sfc_graph_launch", "sfc_graph_destroy",
 ]
@@ -41,7 +41,8 @@ class SfcError(RuntimeError):
 
 class Dims(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_boxes", C.c_int32), ("n_leaf_min", C.c_int32),
-                ("t_cand_max", C.c_int32), ("cand_per_particle", C.c_int32)]
+                ("t_cand_max", C.c_int32), ("cand_per_particle", C.c_int32),
+                ("keep_supersets", C.c_int32)]
 
 
 class CParticles(C.Structure):
@@ -64,7 +65,7 @@ class Verify(C.Structure):
 class DensityParams(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("n_ngb", C.c_int32), ("dn", C.c_int32),
                 ("max_iter", C.c_int32), ("fixed_h", C.c_int32), ("accum", C.c_int32),
-                ("skin", C.c_double), ("t_cand", C.c_int32)]
+                ("skin", C.c_double), ("t_cand", C.c_int32), ("reuse", C.c_int32)]
 
 
 class DensityOut(C.Structure):
@@ -74,7 +75,13 @@ class DensityOut(C.Structure):
 
 class HydroParams(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("gamma", C.c_double), ("alpha", C.c_double),
-                ("accum", C.c_int32), ("t_cand", C.c_int32)]
+                ("accum", C.c_int32), ("t_cand", C.c_int32), ("skin", C.c_double),
+                ("reuse", C.c_int32)]
+
+    def __init__(self, *args, **kw):
+        if len(args) < 6:  # skin defaults to 1 (a group ball of R_g + max h)
+            kw.setdefault("skin", 1.0)
+        super().__init__(*args, **kw)
 
 
 class HydroOut(C.Structure):
@@ -132,6 +139,8 @@ def load_library(path: str = LIB_PATH):
     L.tree_build.restype = I
     L.tree_refit_hmax.argtypes = [_P, PP(CParticles)]
     L.tree_refit_hmax.restype = I
+    L.tree_refit.argtypes = [_P, PP(CParticles)]
+    L.tree_refit.restype = I
     L.group_ngb_search.argtypes = [_P, PP(CParticles), PP(GroupParams), _P, PP(Verify),
                                    C.c_int32]
     L.group_ngb_search.restype = I
@@ -225,7 +234,7 @@ class Context:
     """A library context bound to a torch stream and a device workspace."""
 
     def __init__(self, n: int, n_boxes: int = 1, n_leaf_min: int = 8, t_cand_max: int = 4096,
-                 stream=None, cand_per_particle: int = 0):
+                 stream=None, cand_per_particle: int = 0, keep_supersets: bool = False):
         import torch
         self.L = load_library()
         if not torch.cuda.is_available():
@@ -234,7 +243,7 @@ class Context:
         h = _P()
         self._check(self.L.sfc_ctx_create(C.byref(h), _P(self.stream.cuda_stream)), None)
         self.h = h
-        self.dims = Dims(n, n_boxes, n_leaf_min, t_cand_max, cand_per_particle)
+        self.dims = Dims(n, n_boxes, n_leaf_min, t_cand_max, cand_per_particle, int(keep_supersets))
         nbytes = self.L.sfc_workspace_bytes(C.byref(self.dims))
         if nbytes == 0:
             raise SfcError(SFC_EINVAL, f"invalid workspace dims {n}, {n_boxes}")
@@ -280,6 +289,10 @@ class Context:
     def tree_refit_hmax(self, p: Particles):
         a = p.c()
         self._check(self.L.tree_refit_hmax(self.h, C.byref(a)))
+
+    def tree_refit(self, p: Particles):
+        a = p.c()
+        self._check(self.L.tree_refit(self.h, C.byref(a)))
 
     def group_ngb_search(self, p: Particles, policy=POLICY_PAPER, n_group_max=32, f=0.5,
                          chunk=1024, gp_box=None, verify: Verify | None = None, t_cand=1024,

@@ -69,6 +69,10 @@ def test_workspace_sizes(lib):
     # more boxes and smaller leaves never shrink the layout
     assert lib.sfc_workspace_bytes(C.byref(S.Dims(10 ** 5, 64, 8, 1024))) >= sizes[1]
     assert lib.sfc_workspace_bytes(C.byref(S.Dims(10 ** 5, 1, 1, 1024))) > sizes[1]
+    # kept supersets: a second candidate buffer, group records and snapshots
+    kept = lib.sfc_workspace_bytes(C.byref(S.Dims(10 ** 5, 1, 8, 1024, 0, 1)))
+    assert kept > sizes[1] + 10 ** 5 * (96 * 4 + 2 * 32)
+    assert lib.sfc_workspace_bytes(C.byref(S.Dims(10 ** 5, 1, 8, 1024, 0, 2))) == 0
 
 
 def test_null_context_is_rejected(lib):
@@ -76,6 +80,7 @@ def test_null_context_is_rejected(lib):
     assert lib.sfc_sort(None, C.byref(p), C.byref(p), None, None) == S.SFC_EINVAL
     assert lib.tree_build(None, C.byref(p), None, 8) == S.SFC_EINVAL
     assert lib.tree_refit_hmax(None, C.byref(p)) == S.SFC_EINVAL
+    assert lib.tree_refit(None, C.byref(p)) == S.SFC_EINVAL
     gp = S.GroupParams(1, 8, 0.5, 1024)
     assert lib.group_ngb_search(None, C.byref(p), C.byref(gp), None, None, 1024) == S.SFC_EINVAL
     assert lib.density(None, C.byref(p), C.byref(S.DensityParams()), None) == S.SFC_EINVAL
@@ -90,3 +95,7 @@ def test_null_context_is_rejected(lib):
 def test_binding_imports_without_gpu():
     from paper_1810_09898_amd import pipeline  # noqa: F401
     assert S.POLICY_PAPER == 1 and S.KERNEL_WC6 == 1
+    # the hydro skin defaults to 1 (a group ball of R_g + max h), positional or not
+    assert S.HydroParams().skin == 1.0
+    assert S.HydroParams(1, 5.0 / 3.0, 0.8, 0, 2048).skin == 1.0
+    assert S.HydroParams(1, 5.0 / 3.0, 0.8, 0, 2048, 1.25).skin == 1.25
