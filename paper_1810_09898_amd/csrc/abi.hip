@@ -155,16 +155,19 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     xb.pos4 = b.take<float4>(n);
     xb.snap = nullptr;
     xb.drift = nullptr;
+    xb.sel = nullptr;
     xb.cu_count = c ? c->cu : 0;
     SearchBufs xh = xb;
     if (d.keep_supersets) {
         // the hydro pass gets buffers of its own; snapshots and drift bounds
         xb.snap = b.take<double4>(n);
-        xb.drift = b.take<unsigned long long>(3 + 3 * 512);
+        xb.drift = b.take<unsigned long long>(4 + 3 * 512);
+        xb.sel = b.take<int32_t>(n);
         xh.cand = b.take<int32_t>(xh.cand_cap);
         xh.sup = b.take<GSup>(n);
         xh.snap = b.take<double4>(n);
-        xh.drift = b.take<unsigned long long>(3 + 3 * 512);
+        xh.drift = b.take<unsigned long long>(4 + 3 * 512);
+        xh.sel = xb.sel;
     }
     if (c && base) {
         c->st = st;

@@ -134,7 +134,7 @@ struct DevStatus {
     unsigned long long sum_iters;
     unsigned long long sum_tests;
     unsigned long long sum_pairs;
-    unsigned long long pass_members; // members computed by the last reuse pass
+    int32_t pad[2];
     // Per-pass counters of the search kernels, one per eighth of the work
     // items, each on its own 128-byte line so that the eighths do not
     // serialise on one address: bump pointers of the eight regions of the
@@ -256,8 +256,10 @@ struct SearchBufs {
     float4 *pa, *pb;  // [n] hydro records: (m, v) and (rho, f P / rho^2, c, h)
     float4 *pos4;     // [n] density: FP32 x, y, z and m
     double4 *snap;    // [n] kept supersets: x, y, z (and h) when they were walked, or NULL
-    unsigned long long *drift; // [3 + 3 * 512] largest displacement, largest h growth since
-                               // (FP64 bits), active particles now; per-block partials
+    unsigned long long *drift; // [4 + 3 * 512] largest displacement, largest h growth since
+                               // (FP64 bits), active particles now, members active now;
+                               // then per-block partials
+    int32_t *sel;     // [n] reuse: positions in the active list of the members active now
     int32_t cu_count;
 };
 struct DensityArgs {

@@ -131,7 +131,7 @@ __device__ __forceinline__ unsigned long long uni_u64(unsigned long long v)
 // leaves: a status counter updated by every particle or group would
 // serialise the whole grid on one address.
 struct WaveStats {
-    uint32_t walks = 0, overflow = 0, deferred = 0, iters = 0, not_conv = 0, members = 0;
+    uint32_t walks = 0, overflow = 0, deferred = 0, iters = 0, not_conv = 0;
     unsigned long long cand = 0, tests = 0, pairs = 0;
     __device__ __forceinline__ void flush(DevStatus *st) const
     {
@@ -144,7 +144,6 @@ struct WaveStats {
         if (not_conv) atomicAdd(&st->n_not_converged, (unsigned long long)not_conv);
         if (tests) atomicAdd(&st->sum_tests, tests);
         if (pairs) atomicAdd(&st->sum_pairs, pairs);
-        if (members) atomicAdd(&st->pass_members, (unsigned long long)members);
     }
 };
 
@@ -691,13 +690,36 @@ __global__ void k_reset_pass(DevStatus *st)
         st->cand_top[16 * t] = 0ull;
         st->qctr[32 * t] = 0;
     }
-    if (t == 8) st->pass_members = 0ull;
+}
+
+// Reuse: the positions in the active list of the members whose active flag
+// is set now, appended a wave at a time to sel (count in *cnt, zeroed
+// before); each wave keeps its members in order
+__global__ __launch_bounds__(256) void k_sel_members(const int32_t *__restrict__ n_act,
+                                                     const int32_t *__restrict__ act,
+                                                     const uint8_t *__restrict__ active,
+                                                     int32_t *__restrict__ sel,
+                                                     unsigned long long *__restrict__ cnt)
+{
+    const int A = *n_act;
+    const int lane = lane_id();
+    const int nw = (int)(gridDim.x * blockDim.x) >> 6;
+    for (int a0 = ((int)(blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; a0 < A; a0 += nw << 6) {
+        const int a = a0 + lane;
+        const bool keep = a < A && active[act[a]] != 0;
+        const uint64_t m = ballot(keep);
+        if (!m) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(cnt, (unsigned long long)popc64(m));
+        base = (unsigned long long)readlane_i((int)base, 0);
+        if (keep) sel[base + mbcnt(m)] = a;
+    }
 }
 
 // After a reuse pass: every particle active now was a member of a kept group
 __global__ void k_reuse_check(const unsigned long long *drift, DevStatus *st)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && st->pass_members != drift[2])
+    if (blockIdx.x == 0 && threadIdx.x == 0 && drift[3] != drift[2])
         atomicOr(&st->flags, (unsigned)SFC_ST_REUSE_ACTIVE);
 }
 
@@ -1162,7 +1184,7 @@ struct DensK {
     DevStatus *st;
     int64_t priv; // offset in the candidate buffer of the private slots (T per wave), -1: none
     const unsigned long long *drift; // reused supersets: [0] largest displacement (FP64 bits), or NULL
-    const uint8_t *active;           // reused supersets: members computed now, or NULL
+    const int32_t *sel;              // reused supersets: members computed now (drift[3] of them)
     int n_ngb, dn, max_iter, fixed_h;
 };
 
@@ -1351,15 +1373,13 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
 {
     extern __shared__ __align__(16) char lds_raw[];
     const MemLds S = mem_carve(lds_raw, k.ga.T, true);
-    const int A = uni(*k.ga.n_act);
+    // reuse: the members active now (a list of positions in the active list)
+    const int A = k.sel ? uni((int)k.drift[3]) : uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
     WaveStats ws;
     const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
-    for (int a = ar.i; a < ar.end; a += ar.stride) {
-        if (k.active) { // reuse: the members active now
-            if (!k.active[uni(k.ga.act[a])]) continue;
-            ws.members++;
-        }
+    for (int item = ar.i; item < ar.end; item += ar.stride) {
+        const int a = k.sel ? uni(k.sel[item]) : item;
         Member M = member(k.g, k.ga, k.ca, a);
         double h = M.h, lo = 0.0, hi = INFINITY;
         int it = 0, nn = 0;
@@ -1399,7 +1419,7 @@ struct HydroK {
     const float4 *pb;   // per particle: rho, f P / rho^2, sound speed, h
     const float4 *pos4; // per particle: FP32 x, y, z, h
     const unsigned long long *drift; // reused supersets: largest displacement, h growth, or NULL
-    const uint8_t *active;           // reused supersets: members computed now, or NULL
+    const int32_t *sel;              // reused supersets: members computed now (drift[3] of them)
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
@@ -1664,17 +1684,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
     extern __shared__ __align__(16) char lds_raw[];
     const MemLds S = mem_carve(lds_raw, k.ga.T, false);
     const int lane = lane_id();
-    const int A = uni(*k.ga.n_act);
+    const int A = k.sel ? uni((int)k.drift[3]) : uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
     WaveStats ws;
     // reused supersets: the largest displacement and h growth since the walk
     const double dl = k.drift ? __longlong_as_double((long long)k.drift[0]) : 0.0;
     const double dh = k.drift ? __longlong_as_double((long long)k.drift[1]) : 0.0;
-    for (int a = ar.i; a < ar.end; a += ar.stride) {
-        if (k.active) { // reuse: the members active now
-            if (!k.active[uni(k.ga.act[a])]) continue;
-            ws.members++;
-        }
+    for (int item = ar.i; item < ar.end; item += ar.stride) {
+        const int a = k.sel ? uni(k.sel[item]) : item;
         const Member M = member(k.g, k.ga, k.ca, a);
         const bool kept = !k.drift || (M.h + M.d + dl <= M.s.cov && M.d + dl + dh <= M.s.rs);
         if ((M.s.flags & GSUP_SOLO) || !kept) {
@@ -1978,14 +1995,21 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
 }
 
 // the drift bounds of kept supersets and the active count into
-// sb.drift[0..2] (h: NULL for none)
-hipError_t launch_drift(hipStream_t s, const PartDev &p, const double *h, const SearchBufs &sb)
+// sb.drift[0..2] (h: NULL for none); the members active now into sb.sel,
+// their count into sb.drift[3]
+hipError_t launch_drift(hipStream_t s, const PartDev &p, const double *h, const GroupBufs &g,
+                        const SearchBufs &sb)
 {
     k_drift_part<<<DRIFT_BLOCKS, 256, 0, s>>>(p.n, p.nb, p.box_off, p.box_L, p.x, p.y, p.z, h,
-                                              p.active, sb.snap, sb.drift + 3);
+                                              p.active, sb.snap, sb.drift + 4);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_drift_final<<<1, 256, 0, s>>>(sb.drift + 3, sb.drift);
+    k_drift_final<<<1, 256, 0, s>>>(sb.drift + 4, sb.drift);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_fill_i32(s, (int32_t *)(sb.drift + 3), 0, 2)) != hipSuccess) return e;
+    const int64_t wg = (p.n + 255) / 256;
+    k_sel_members<<<(unsigned)(wg < 4096 ? wg : 4096), 256, 0, s>>>(g.n_act, g.act, p.active, sb.sel,
+                                                                   sb.drift + 3);
     return hipGetLastError();
 }
 } // namespace
@@ -2019,7 +2043,7 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     if (dp.reuse) {
         // the kept supersets: the walk is skipped, the drift bounds them
         k_reset_pass<<<1, 64, 0, s>>>(st);
-        e = launch_drift(s, p, nullptr, sb);
+        e = launch_drift(s, p, nullptr, g, sb);
     } else {
         e = launch_walk(s, p, t, g, gs, st, dp.t_cand, dp.skin, 0);
     }
@@ -2041,7 +2065,7 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
     k.drift = dp.reuse ? sb.drift : nullptr;
-    k.active = dp.reuse ? p.active : nullptr;
+    k.sel = dp.reuse ? sb.sel : nullptr;
     kern<<<grid, th, lds, s>>>(k);
     e = hipGetLastError();
     if (e != hipSuccess || !dp.reuse) return e;
@@ -2072,7 +2096,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     if (e != hipSuccess) return e;
     if (hp.reuse) {
         k_reset_pass<<<1, 64, 0, s>>>(st);
-        e = launch_drift(s, p, p.h, sb);
+        e = launch_drift(s, p, p.h, g, sb);
     } else {
         e = launch_walk(s, p, t, g, sb, st, hp.t_cand, hp.skin, 1);
     }
@@ -2097,7 +2121,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
     k.drift = hp.reuse ? sb.drift : nullptr;
-    k.active = hp.reuse ? p.active : nullptr;
+    k.sel = hp.reuse ? sb.sel : nullptr;
     const size_t lds = MEM_WAVES * mem_lds_bytes(hp.t_cand, false);
     const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;

@@ -13,6 +13,9 @@ density + hydro, and the status counters of one step.
   a HIP graph and replayed, and the FP32-compensated results compared with
   the FP64-accumulator variant on the GPU (relative errors per field).
 - the other workloads: one line.
+- --workload lognormal_bins --reuse-bins SKIN: bins 1 and 2 on the
+  supersets kept by the full step (all active) after a drift (the first of
+  FRACS), beside the ordinary bin steps.
 - --reuse SKINS: superset reuse after a drift.  Per skin, a walking step that
   keeps its supersets, then per drift (the fastest particle moving FRACS times
   the smallest h, as in a global step limited by the Courant condition;
@@ -203,6 +206,60 @@ def reuse_scan(w, cfg, steps, skins, fracs):
         del pl
 
 
+def reuse_bins(w, steps, skin, frac):
+    """The finer bins of lognormal_bins on the supersets kept by the full
+    step (all active, skin), after a drift of frac times the smallest h,
+    beside the ordinary bin steps (sort, tree, groups, walks)."""
+    import torch
+    from .pipeline import Pipeline
+    base = dict(w.state)
+    ordinary = {}
+    for b in (1, 2):
+        w.state = dict(base)
+        w.state["active"] = (base["bin"] >= b).astype(np.uint8)
+        pl = Pipeline(w, BIN_CONFIGS[b])
+        pl.step()
+        ph = _phases(pl, steps)
+        ordinary[b] = (sum(ph.values()), ph)
+        del pl
+        torch.cuda.empty_cache()
+    w.state = dict(base)
+    w.state["active"] = np.ones(w.n, np.uint8)
+    c = BIN_CONFIGS[0]
+    c = c.with_(skin=skin, hydro_skin=skin, keep_supersets=True, t_cand=2 * c.t_cand,
+                hydro_t_cand=2 * c.hydro_t_cand)
+    pl = Pipeline(w, c)
+    pl.step()
+    ph_keep = _phases(pl, steps)
+    t = pl.ps.t
+    x0, y0, z0, h0 = (t[k].clone() for k in ("x", "y", "z", "h"))
+    Lp = float(w.box_L[0])
+    v = torch.sqrt(t["vx"].double() ** 2 + t["vy"].double() ** 2 + t["vz"].double() ** 2)
+    dt = frac * float(torch.min(h0)) / float(v.max())
+    for k, k0, vk in (("x", x0, "vx"), ("y", y0, "vy"), ("z", z0, "vz")):
+        a = torch.remainder(k0 + dt * t[vk].double(), Lp)
+        t[k].copy_(torch.where(a >= Lp, a - Lp, a))
+    bins = torch.as_tensor(base["bin"], device="cuda")[t["orig"].long()]
+    print(json.dumps({"workload": w.name, "kind": "full step keeping its supersets", "skin": skin,
+                      "step_ms": round(sum(ph_keep.values()), 4), "phases_ms": ph_keep}), flush=True)
+    for b in (1, 2):
+        t["active"].copy_((bins >= b).to(torch.uint8))
+        A = int((bins >= b).sum())
+        pl.ctx.status_clear()
+        t["h"].copy_(h0)
+        pl.reuse_step()
+        torch.cuda.synchronize()
+        st = pl.ctx.status(raise_on_overflow=False)
+        ph_r = _reuse_phases(pl, h0, steps)
+        tr = sum(ph_r.values())
+        print(json.dumps({
+            "workload": w.name, "kind": "bin reuse", "bin": b, "n_active": A, "skin": skin,
+            "drift_frac_min_h": frac, "reuse_step_ms": round(tr, 4), "reuse_phases_ms": ph_r,
+            "ordinary_step_ms": round(ordinary[b][0], 4), "ordinary_phases_ms": ordinary[b][1],
+            "speedup": round(ordinary[b][0] / tr, 3), "status": st}), flush=True)
+    del pl
+
+
 def _bin_configs():
     from .pipeline import StepConfig
     # chosen by autotune.py (`--workload lognormal_bins --bins 0,1,2`)
@@ -216,6 +273,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--reuse", default="", help="comma-separated skins: superset reuse scan")
     ap.add_argument("--fracs", default="0.05,0.1,0.3")
+    ap.add_argument("--reuse-bins", type=float, default=0.0,
+                    help="skin: finer bins of lognormal_bins on the full step's supersets")
     args = ap.parse_args()
     from . import workloads as W
     from . import autotune
@@ -227,7 +286,9 @@ def main():
     w = W.WORKLOADS[args.workload]()
     print(f"# {args.workload}: generated in {time.time() - t0:.1f} s, n={w.n}", file=sys.stderr,
           flush=True)
-    if args.reuse:
+    if args.reuse_bins:
+        reuse_bins(w, args.steps, args.reuse_bins, float(args.fracs.split(",")[0]))
+    elif args.reuse:
         cfg = StepConfig(n_leaf=128, n_group_max=24, f=0.5, t_cand=2048, hydro_t_cand=2048)
         reuse_scan(w, cfg, args.steps, [float(v) for v in args.reuse.split(",")],
                    [float(v) for v in args.fracs.split(",")])

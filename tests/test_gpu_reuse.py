@@ -19,6 +19,11 @@ from paper_1810_09898_amd.pipeline import Pipeline, StepConfig
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
+# The drifted positions are off the generator's 2^-24 grid, so their FP32
+# copies are rounded: the FP32 pair displacement is off by a few 2^-24 L, and
+# the signal speed's projection w_ij = v_ij . r_ij / r by that over r (a few
+# 1e-6 for the closest pairs; 1.6e-6 measured).  On the grid it is 1e-6.
+TOL_VSIG = 1e-5
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -150,7 +155,7 @@ def test_reuse_after_drift(frac, ref, skin, logn, sorted_ref):
     for k, ref, A in (("ax", hr.ax, hr.abs_a), ("ay", hr.ay, hr.abs_a), ("az", hr.az, hr.abs_a),
                       ("dudt", hr.dudt, hr.abs_du)):
         assert np.max(np.abs(hre[k][act] - ref) / A) < 2 * TOL32, k
-    assert np.max(np.abs(hre["vsigmax"][act] / hr.vsigmax - 1)) < 1e-6
+    assert np.max(np.abs(hre["vsigmax"][act] / hr.vsigmax - 1)) < TOL_VSIG
     pl.hydro_force(reuse=False)
     hw = outputs(pl, HKEYS)
     for k in HKEYS:
@@ -275,6 +280,11 @@ def test_reuse_errors(logn):
     assert e.value.code == S.SFC_EORDER
     pk = Pipeline(logn, StepConfig(n_group_max=32, t_cand=1024, keep_supersets=True))
     pk.step()
+    pk.hp.skin = 0.5
+    with pytest.raises(S.SfcError) as e:
+        pk.hydro_force()
+    assert e.value.code == S.SFC_EINVAL
+    pk.hp.skin = 1.0
     pk.dp.t_cand = 512
     with pytest.raises(S.SfcError) as e:
         pk.density(reuse=True)
@@ -287,7 +297,3 @@ def test_reuse_errors(logn):
     with pytest.raises(S.SfcError) as e:
         pk.hydro_force(reuse=True)
     assert e.value.code == S.SFC_EORDER
-    pk.hp.skin = 0.5
-    with pytest.raises(S.SfcError) as e:
-        pk.hydro_force()
-    assert e.value.code == S.SFC_EINVAL
