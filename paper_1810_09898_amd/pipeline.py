@@ -46,11 +46,12 @@ class Pipeline:
     def __init__(self, w, cfg: StepConfig, hydro: bool | None = None, gp_box=None,
                  cand_per_particle: int | None = None):
         """cand_per_particle: capacity of the superset buffer per particle; by
-        default 1.5 N_ngb per active particle (an ungrouped pass fits), at
-        least 96."""
+        default 1.5 N_ngb per active particle (an ungrouped pass fits), times
+        skin^3 for a skin wider than 1, at least 96."""
         import torch
         if cand_per_particle is None:
-            per_act = 1.5 * w.n_ngb * float(np.count_nonzero(w.state["active"])) / max(w.n, 1)
+            grow = max(cfg.skin, cfg.hydro_skin) ** 3
+            per_act = 1.5 * grow * w.n_ngb * float(np.count_nonzero(w.state["active"])) / max(w.n, 1)
             cand_per_particle = int(min(4096, max(96, math.ceil(per_act) + 16)))
         self.w = w
         self.cfg = cfg

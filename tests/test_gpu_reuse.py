@@ -243,6 +243,89 @@ def test_reuse_finer_bin(logn, sorted_ref):
     assert pl.ctx.status()["flags"] & S.ST_REUSE_ACTIVE
 
 
+def test_reuse_batch_of_boxes():
+    """Six periodic boxes in one launch: the drift bound takes each
+    particle's displacement in its own box (minimum image), and the reuse
+    matches the oracle box by box."""
+    say("[reuse] batch of 6 boxes")
+    import torch
+    w = W.plummer_batch(n_boxes=6, seed0=1000, n_range=(2000, 30000))
+    ob = oracle.Boxes(w.box_off, w.box_L)
+    keys, perm, s = oracle.sorted_state(w.state, ob)
+    act = np.nonzero(s["active"])[0]
+    # the step before has converged h (the oracle's), as in a running simulation
+    h1 = s["h"].copy()
+    h1[act] = oracle.density(s["x"], s["y"], s["z"], s["h"], s["m"], ob, act, w.kernel, w.n_ngb,
+                             w.dn).h
+    w.state["h"] = w.state["h"].copy()
+    w.state["h"][perm] = h1
+    pl = Pipeline(w, StepConfig(n_leaf=16, n_group_max=16, f=0.5, t_cand=1024, skin=1.1,
+                                keep_supersets=True), cand_per_particle=256)
+    pl.step()
+    torch.cuda.synchronize()
+    st = pl.ctx.status(raise_on_overflow=False)
+    say(f"  walking step: overflow {st['n_overflow']}, deferred {st['n_deferred']}")
+    assert st["flags"] == 0 and st["n_overflow"] == 0
+    # random displacements, the largest 0.1 of the smallest h; every box has L = 1
+    rng = np.random.default_rng(11)
+    disp = rng.normal(size=(3, w.n))
+    disp *= 0.1 * float(s["h"].min()) / float(np.sqrt((disp ** 2).sum(0)).max())
+    d = {}
+    for c, dc in zip("xyz", disp):
+        a_ = np.mod(s[c] + dc, 1.0)
+        a_[a_ >= 1.0] -= 1.0
+        d[c] = a_
+    r = oracle.density(d["x"], d["y"], d["z"], h1, s["m"], ob, act, w.kernel, w.n_ngb, w.dn)
+    upload(pl, x=d["x"], y=d["y"], z=d["z"], h=h1)
+    pl.ctx.status_clear()
+    pl.reuse_step()
+    dr = outputs(pl, DKEYS)
+    st = pl.ctx.status()
+    assert st["flags"] == 0
+    say(f"  walks {st['n_walks']}, deferred {st['n_deferred']} of {len(act)}")
+    assert st["n_deferred"] < len(act) // 10
+    assert np.array_equal(dr["h"][act], r.h)
+    assert np.array_equal(dr["nngb"][act], r.nngb)
+    assert np.max(np.abs(dr["rho"][act] / r.rho - 1)) < TOL32
+
+
+def test_reuse_step_in_a_graph(logn, sorted_ref):
+    """The reuse step (refit, density, hydro on the kept supersets) captured
+    as one HIP graph: every replay gives the eager bits."""
+    say("[reuse] graph capture and replay")
+    import torch
+    ob, perm, s, act = sorted_ref
+    L = float(logn.box_L[0])
+    d = drifted(s, L, 0.1)
+    st_ = torch.cuda.Stream()
+    with torch.cuda.stream(st_):
+        pl = Pipeline(logn, StepConfig(n_leaf=128, n_group_max=32, skin=1.1, hydro_skin=1.1,
+                                       t_cand=4096, hydro_t_cand=4096, keep_supersets=True))
+        pl.step()
+        st_.synchronize()
+        h1 = pl.ps.t["h"].clone()
+        upload(pl, x=d["x"], y=d["y"], z=d["z"])
+        pl.reuse_step()
+        ref = outputs(pl, DKEYS + HKEYS)
+        pl.ps.t["h"].copy_(h1)
+        pl.ctx.graph_begin()
+        pl.reuse_step()
+        g = pl.ctx.graph_end()
+        try:
+            for rep in range(3):
+                for t in pl.o.values():
+                    t.zero_()
+                pl.ps.t["h"].copy_(h1)
+                pl.ctx.graph_launch(g)
+                st_.synchronize()
+                got = outputs(pl, DKEYS + HKEYS)
+                for k in DKEYS + HKEYS:
+                    assert np.array_equal(ref[k], got[k]), (rep, k)
+        finally:
+            pl.ctx.graph_destroy(g)
+        assert pl.ctx.status()["flags"] == 0
+
+
 def test_status_clear_keeps_the_tree(logn):
     """Clearing the status counters between the tree and the hydro pass
     keeps the node count that the refits read: the same bits either way."""
