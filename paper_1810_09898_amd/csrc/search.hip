@@ -693,8 +693,11 @@ __global__ void k_reset_pass(DevStatus *st)
 }
 
 // Reuse: the positions in the active list of the members whose active flag
-// is set now, appended a wave at a time to sel (count in *cnt, zeroed
-// before); each wave keeps its members in order
+// is set now, appended to sel (count in *cnt, zeroed before).  A wave takes
+// SEL_CH consecutive blocks of 64 members, counts them, reserves their
+// slots with one atomic (a single counter serialises its atomics) and
+// writes them in order.
+constexpr int SEL_CH = 8;
 __global__ __launch_bounds__(256) void k_sel_members(const int32_t *__restrict__ n_act,
                                                      const int32_t *__restrict__ act,
                                                      const uint8_t *__restrict__ active,
@@ -704,15 +707,25 @@ __global__ __launch_bounds__(256) void k_sel_members(const int32_t *__restrict__
     const int A = *n_act;
     const int lane = lane_id();
     const int nw = (int)(gridDim.x * blockDim.x) >> 6;
-    for (int a0 = ((int)(blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; a0 < A; a0 += nw << 6) {
-        const int a = a0 + lane;
-        const bool keep = a < A && active[act[a]] != 0;
-        const uint64_t m = ballot(keep);
-        if (!m) continue;
+    const int wv = (int)(blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    for (int c0 = wv * 64 * SEL_CH; c0 < A; c0 += nw * 64 * SEL_CH) {
+        uint64_t m[SEL_CH];
+        int total = 0;
+#pragma unroll
+        for (int u = 0; u < SEL_CH; u++) {
+            const int a = c0 + 64 * u + lane;
+            m[u] = ballot(a < A && active[act[a < A ? a : 0]] != 0);
+            total += popc64(m[u]);
+        }
+        if (total == 0) continue;
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(cnt, (unsigned long long)popc64(m));
-        base = (unsigned long long)readlane_i((int)base, 0);
-        if (keep) sel[base + mbcnt(m)] = a;
+        if (lane == 0) base = atomicAdd(cnt, (unsigned long long)total);
+        int b = readlane_i((int)base, 0);
+#pragma unroll
+        for (int u = 0; u < SEL_CH; u++) {
+            if ((m[u] >> lane) & 1ull) sel[b + mbcnt(m[u])] = c0 + 64 * u + lane;
+            b += popc64(m[u]);
+        }
     }
 }
 
@@ -2007,7 +2020,7 @@ hipError_t launch_drift(hipStream_t s, const PartDev &p, const double *h, const 
     k_drift_final<<<1, 256, 0, s>>>(sb.drift + 4, sb.drift);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_fill_i32(s, (int32_t *)(sb.drift + 3), 0, 2)) != hipSuccess) return e;
-    const int64_t wg = (p.n + 255) / 256;
+    const int64_t wg = (p.n + 256 * SEL_CH - 1) / (256 * SEL_CH);
     k_sel_members<<<(unsigned)(wg < 4096 ? wg : 4096), 256, 0, s>>>(g.n_act, g.act, p.active, sb.sel,
                                                                    sb.drift + 3);
     return hipGetLastError();
