@@ -134,7 +134,7 @@ struct DevStatus {
     unsigned long long sum_iters;
     unsigned long long sum_tests;
     unsigned long long sum_pairs;
-    int32_t pad[2];
+    unsigned long long n_dfr; // per pass: hydro members deferred to their own walks
     // Per-pass counters of the search kernels, one per eighth of the work
     // items, each on its own 128-byte line so that the eighths do not
     // serialise on one address: bump pointers of the eight regions of the
@@ -260,6 +260,7 @@ struct SearchBufs {
                                // (FP64 bits), active particles now, members active now;
                                // then per-block partials
     int32_t *sel;     // [n] reuse: positions in the active list of the members active now
+    int32_t *dfr;     // [n] hydro: positions in the active list of the members that walk alone
     int32_t cu_count;
 };
 struct DensityArgs {

@@ -690,6 +690,7 @@ __global__ void k_reset_pass(DevStatus *st)
         st->cand_top[16 * t] = 0ull;
         st->qctr[32 * t] = 0;
     }
+    if (t == 8) st->n_dfr = 0ull;
 }
 
 // Reuse: the positions in the active list of the members whose active flag
@@ -1433,6 +1434,7 @@ struct HydroK {
     const float4 *pos4; // per particle: FP32 x, y, z, h
     const unsigned long long *drift; // reused supersets: largest displacement, h growth, or NULL
     const int32_t *sel;              // reused supersets: members computed now (drift[3] of them)
+    int32_t *dfr;                    // members that walk alone (st->n_dfr of them)
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
@@ -1709,6 +1711,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
         const bool kept = !k.drift || (M.h + M.d + dl <= M.s.cov && M.d + dl + dh <= M.s.rs);
         if ((M.s.flags & GSUP_SOLO) || !kept) {
             ws.deferred++;
+            if (k.drift) { // reuse (many members may walk alone): in k_hydro_solo
+                if (lane == 0) k.dfr[atomicAdd(&k.st->n_dfr, 1ull)] = a;
+                continue;
+            }
             HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
             StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
                                                    M.bx.L, M.h, M.i, FifoH{(HEnt *)S.fifo, 0}, &hp};
@@ -1777,6 +1783,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
             }
         }
         q.flush(hp);
+        hydro_write<KER, ACC>(k, M.i, hp);
+    }
+    ws.flush(k.st);
+}
+
+// The hydro members that a reuse call of k_hydro deferred (their group kept
+// no superset, or the reused one no longer covers them): one wave each walks
+// the tree level by level and streams its pairs into the sums.  A kernel of
+// their own keeps that walk out of k_hydro's register budget; the few
+// members of an ordinary call walk inside k_hydro (window walk), where their
+// walks overlap the other waves' work.
+constexpr int HSOLO_WAVE_LDS = FIFO_BYTES + 4 * (2 * LCAP + 64);
+template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro_solo(HydroK k)
+{
+    extern __shared__ __align__(16) char lds_raw[];
+    const int wave = uni((int)(threadIdx.x >> 6));
+    MemLds S;
+    S.masks = nullptr;
+    S.fifo = (void *)(lds_raw + (size_t)wave * HSOLO_WAVE_LDS);
+    S.r2c = (float *)((char *)S.fifo + FIFO_BYTES);
+    S.rc = 2 * LCAP + 64;
+    const int D = uni((int)k.st->n_dfr);
+    const ItemRange ar = item_range(D);
+    WaveStats ws;
+    for (int item = ar.i; item < ar.end; item += ar.stride) {
+        const Member M = member(k.g, k.ga, k.ca, uni(k.dfr[item]));
+        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
+        StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
+                                               M.bx.L, M.h, M.i, FifoH{(HEnt *)S.fifo, 0}, &hp};
+        Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
+        solo_walk(k.g, S, M, B, sv, k.st);
+        ws.walks++;
+        sv.q.flush(hp);
         hydro_write<KER, ACC>(k, M.i, hp);
     }
     ws.flush(k.st);
@@ -2135,17 +2174,28 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.alpha = hp.alpha;
     k.drift = hp.reuse ? sb.drift : nullptr;
     k.sel = hp.reuse ? sb.sel : nullptr;
+    k.dfr = sb.dfr;
     const size_t lds = MEM_WAVES * mem_lds_bytes(hp.t_cand, false);
+    const size_t lds_s = (size_t)MEM_WAVES * HSOLO_WAVE_LDS;
     const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;
-    if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32)
+    if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32) {
         e = launch_persistent(k_hydro<0, float>, s, k, th, lds, sb.cu_count, n);
-    else if (hp.kernel == 0)
+        if (e == hipSuccess && hp.reuse)
+            e = launch_persistent(k_hydro_solo<0, float>, s, k, th, lds_s, sb.cu_count, n);
+    } else if (hp.kernel == 0) {
         e = launch_persistent(k_hydro<0, double>, s, k, th, lds, sb.cu_count, n);
-    else if (hp.accum == SFC_ACCUM_F32)
+        if (e == hipSuccess && hp.reuse)
+            e = launch_persistent(k_hydro_solo<0, double>, s, k, th, lds_s, sb.cu_count, n);
+    } else if (hp.accum == SFC_ACCUM_F32) {
         e = launch_persistent(k_hydro<1, float>, s, k, th, lds, sb.cu_count, n);
-    else
+        if (e == hipSuccess && hp.reuse)
+            e = launch_persistent(k_hydro_solo<1, float>, s, k, th, lds_s, sb.cu_count, n);
+    } else {
         e = launch_persistent(k_hydro<1, double>, s, k, th, lds, sb.cu_count, n);
+        if (e == hipSuccess && hp.reuse)
+            e = launch_persistent(k_hydro_solo<1, double>, s, k, th, lds_s, sb.cu_count, n);
+    }
     if (e != hipSuccess || !hp.reuse) return e;
     k_reuse_check<<<1, 64, 0, s>>>(sb.drift, st);
     return hipGetLastError();
