@@ -162,6 +162,52 @@ def test_reuse_after_drift(frac, ref, skin, logn, sorted_ref):
         assert np.array_equal(hre[k], hw[k]), k
 
 
+def test_reuse_fp64_sums(logn, sorted_ref):
+    """The FP64-accumulator kernels on kept supersets, skin 1 (many hydro
+    members outgrow theirs and walk in the pass of their own): within 1e-12
+    of the oracle."""
+    say("[reuse] FP64 sums, skin 1.0")
+    import torch
+    ob, perm, s, act = sorted_ref
+    w = logn
+    L = float(w.box_L[0])
+    pl = Pipeline(w, StepConfig(n_leaf=128, n_group_max=32, accum=S.ACCUM_F64, keep_supersets=True))
+    pl.step()
+    torch.cuda.synchronize()
+    h1 = s["h"].copy()
+    h1[act] = oracle.density(s["x"], s["y"], s["z"], s["h"], s["m"], ob, act, w.kernel, w.n_ngb,
+                             w.dn, use_grid=True).h
+    d = drifted(s, L, 0.1)
+    r = oracle.density(d["x"], d["y"], d["z"], h1, s["m"], ob, act, w.kernel, w.n_ngb, w.dn,
+                       use_grid=True)
+    upload(pl, x=d["x"], y=d["y"], z=d["z"], h=h1)
+    pl.refit()
+    pl.density(reuse=True)
+    o = outputs(pl, ("h", "rho64"))
+    assert np.array_equal(o["h"][act], r.h)
+    assert np.max(np.abs(o["rho64"][act] / r.rho - 1)) < 1e-12
+    h = h1.copy()
+    rho = s["rho"].astype(np.float64)
+    fg = s["fgrad"].astype(np.float64)
+    h[act], rho[act], fg[act] = r.h, r.rho, r.fgrad
+    # rho and f enter the hydro pass as FP32 fields: both sides take the FP32 values
+    rho32 = rho.astype(np.float32).astype(np.float64)
+    fg32 = fg.astype(np.float32).astype(np.float64)
+    hr = oracle.hydro(d["x"], d["y"], d["z"], h, s["m"], s["vx"], s["vy"], s["vz"], s["u"], rho32,
+                      fg32, ob, act, w.kernel, use_grid=True)
+    upload(pl, h=h, rho=rho32, fgrad=fg32)
+    pl.ctx.status_clear()
+    pl.hydro_force(reuse=True)
+    ho = outputs(pl, ("ax64", "ay64", "az64", "dudt64"))
+    st = pl.ctx.status()
+    assert st["flags"] == 0
+    say(f"  hydro deferred {st['n_deferred']} of {len(act)}")
+    assert st["n_deferred"] > 0
+    for k, ref, A in (("ax64", hr.ax, hr.abs_a), ("ay64", hr.ay, hr.abs_a), ("az64", hr.az, hr.abs_a),
+                      ("dudt64", hr.dudt, hr.abs_du)):
+        assert np.max(np.abs(ho[k][act] - ref) / A) < 1e-12, k
+
+
 def test_reuse_twice_in_a_row(logn, sorted_ref):
     """Two drifts on the same kept supersets: the bound is taken from the
     snapshot of the walk, not from the previous reuse."""
