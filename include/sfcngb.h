@@ -234,7 +234,14 @@ typedef struct {
  * bin (a subset of the grouped particles) reuses the supersets of the step
  * that grouped them all; an active particle outside the kept groups sets
  * SFC_ST_REUSE_ACTIVE.  Results are those of a walking call.  sfc_sort,
- * tree_build and group_ngb_search drop the kept supersets. */
+ * tree_build and group_ngb_search drop the kept supersets.
+ * The particle arrays are the ones the walking call saw, in the same order
+ * (moved in place by the caller).  hydro_force with reuse = 1 refits the
+ * node boxes itself; density needs tree_refit first.  Errors (host side,
+ * nothing enqueued): SFC_EORDER when no superset is kept, SFC_EINVAL for a
+ * t_cand other than the walking call's.  keep_supersets enlarges the
+ * workspace (a second candidate buffer and group records, snapshots);
+ * sfc_workspace_bytes includes it. */
 
 /* Density pass over the active particles of the last group_ngb_search
  * (sections "Phases of Neighbour Search" and "Adaptive Neighbour
