@@ -474,8 +474,10 @@ def test_lattice_density(kernel, s2):
     assert np.allclose(r.rho, want, rtol=1e-13, atol=0)
 
 
-def test_lattice_density_survey_values():
-    # n = 32 lattice: cubic (h/a)^2 = 6.5 and Wendland C6 (h/a)^2 = 20.5
+def test_lattice_density_tabulated_values():
+    # n = 32 lattice: cubic (h/a)^2 = 6.5 and Wendland C6 (h/a)^2 = 20.5; the
+    # values are the kernel sums over the integer points inside h, evaluated
+    # to eight digits independently of the oracle
     for kernel, s2, want in ((0, 6.5, 0.99769611), (1, 20.5, 1.00006414)):
         n = 32
         x, y, z, a = _lattice(n)
