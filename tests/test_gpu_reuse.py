@@ -396,6 +396,27 @@ def test_status_clear_keeps_the_tree(logn):
         assert np.array_equal(outs[0][k], outs[1][k]), k
 
 
+def test_reuse_with_no_member_active(logn, sorted_ref):
+    """A reuse call when no particle is active: nothing is computed, nothing
+    flagged, every output untouched."""
+    say("[reuse] no member active now")
+    import torch
+    ob, perm, s, act = sorted_ref
+    pl = Pipeline(logn, StepConfig(n_leaf=128, n_group_max=32, skin=1.1, hydro_skin=1.1,
+                                   keep_supersets=True))
+    pl.step()
+    torch.cuda.synchronize()
+    before = outputs(pl, DKEYS + HKEYS)
+    upload(pl, active=np.zeros(logn.n, np.uint8))
+    pl.ctx.status_clear()
+    pl.reuse_step()
+    after = outputs(pl, DKEYS + HKEYS)
+    st = pl.ctx.status()
+    assert st["flags"] == 0 and st["n_walks"] == 0 and st["sum_pairs"] == 0
+    for k in DKEYS + HKEYS:
+        assert np.array_equal(before[k], after[k]), k
+
+
 def test_reuse_errors(logn):
     """Reuse without kept supersets, after a new sort, or with another tile
     is refused on the host."""
