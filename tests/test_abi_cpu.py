@@ -99,3 +99,18 @@ def test_binding_imports_without_gpu():
     assert S.HydroParams().skin == 1.0
     assert S.HydroParams(1, 5.0 / 3.0, 0.8, 0, 2048).skin == 1.0
     assert S.HydroParams(1, 5.0 / 3.0, 0.8, 0, 2048, 1.25).skin == 1.25
+
+
+def test_step_parameters_marshalling():
+    """The pipeline's parameter blocks carry the step configuration, the
+    hydro skin and the reuse flags into the C structs (host logic only)."""
+    from types import SimpleNamespace as NS
+    from paper_1810_09898_amd.pipeline import Pipeline, StepConfig
+    cfg = StepConfig(skin=1.1, hydro_skin=1.25, t_cand=1024, hydro_t_cand=4096,
+                     keep_supersets=True)
+    pl = NS(cfg=cfg, w=NS(kernel=1, n_ngb=295, dn=6, fixed_h=False), o={}, hydro=True)
+    Pipeline._build_params(pl)
+    assert (pl.dp.kernel, pl.dp.n_ngb, pl.dp.dn, pl.dp.t_cand) == (1, 295, 6, 1024)
+    assert pl.dp.skin == 1.1 and pl.dp.reuse == 0
+    assert pl.hp.skin == 1.25 and pl.hp.t_cand == 4096 and pl.hp.reuse == 0
+    assert abs(pl.hp.gamma - 5.0 / 3.0) < 1e-15 and pl.hp.alpha == 0.8
