@@ -120,6 +120,23 @@ typedef struct {
 SFC_API int sfc_sort(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out, uint64_t *keys_out,
              uint32_t *perm_out);
 
+/* The sort of sfc_sort without any device allocation or bound workspace,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and the same results, bit for bit, as sfc_sort; the records,
+ * keys, payloads and histograms live in a static device array of
+ * SFC_STATIC_SCRATCH_BYTES that the library holds on every device it runs on
+ * (from the first sfc_ctx_create there) until the process ends.  Limit:
+ * 1 <= in->n <= SFC_SORT_STATIC_MAX_N, else SFC_EINVAL with nothing
+ * enqueued.  Every call on one device shares that device's scratch: calls
+ * that overlap on one device (other streams, other contexts) race, so
+ * serialise them.  Leaves the context's tree, groups and kept supersets as
+ * they were. */
+#define SFC_STATIC_SCRATCH_BYTES (32u << 20)
+#define SFC_SORT_STATIC_MAX_N 262144
+SFC_API int sfc_sort_static(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out,
+                            uint64_t *keys_out, uint32_t *perm_out);
+
 /* Octree over sorted particles (the tree of section "Neighbour Search in
  * Gadget3"): a node is a non-empty Hilbert cell (keys sharing the top 3l bits
  * at level l), the box is the root, a node with <= n_leaf particles (or at

@@ -4,8 +4,40 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
+
+// Device scratch of sfc_sort_static: a file-scope array that every device
+// the library runs on holds until the process ends.  Host code never uses
+// the name `scratch` as an address: its device address is looked up once per
+// device (sfc_ctx_create, with that device current) and kept in g_scratch.
+static __device__ __align__(256) char scratch[SFC_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES];      // device address of `scratch` on each device
+hipError_t g_scratch_err[MAX_DEVICES];
+
+// the address of `scratch` on the current device `dev` (looked up once)
+void *scratch_resolve(int dev, hipError_t *err)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev] && g_scratch_err[dev] == hipSuccess) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && ptr) g_scratch[dev] = ptr;
+        else g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch[dev];
+}
+} // namespace
 
 hipError_t launch_gather(hipStream_t s, const sfc_particles *in, sfc_particles *out,
                          const uint32_t *perm, uint32_t *perm_out);
@@ -37,6 +69,8 @@ struct sfc_ctx {
     int have_groups;
     int kept_d, kept_h; // t_cand of the kept density / hydro supersets, 0 = none
     bool capturing;
+    void *scratch;  // device address of the static scratch on this device (or NULL)
+    hipError_t scratch_err;
 };
 
 struct sfc_graph {
@@ -90,6 +124,24 @@ int64_t cand_capacity(const sfc_dims &d)
     return per * d.n + 64 * (int64_t)d.t_cand_max;
 }
 
+// the sort's buffers (records, double-buffered keys, payloads and box ids,
+// tile histograms) for n particles in nb boxes
+SortBufs carve_sort(Bump &b, int64_t n, int64_t nb)
+{
+    SortBufs sb;
+    const int64_t nt = (n + 4095) / 4096;
+    sb.rec = b.take<PRec>(n);
+    sb.key_a = b.take<uint64_t>(n);
+    sb.key_b = b.take<uint64_t>(n);
+    sb.val_a = b.take<uint32_t>(n);
+    sb.val_b = b.take<uint32_t>(n);
+    sb.box_a = b.take<uint32_t>(nb > 1 ? n : 1);
+    sb.box_b = b.take<uint32_t>(nb > 1 ? n : 1);
+    sb.hist = b.take<uint32_t>(2 * 256 * nt);
+    sb.scan_tmp = nullptr;
+    return sb;
+}
+
 bool dims_ok(const sfc_dims *d)
 {
     return d && d->n >= 1 && d->n < ((int64_t)1 << 30) && d->n_boxes >= 1 &&
@@ -106,15 +158,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     int64_t n = d.n, nb = d.n_boxes, cap = node_capacity(d), mc = max_chunks(d);
     int64_t nt = sort_tiles(d);
     DevStatus *st = b.take<DevStatus>(1);
-    SortBufs sb;
-    sb.rec = b.take<PRec>(n);
-    sb.key_a = b.take<uint64_t>(n);
-    sb.key_b = b.take<uint64_t>(n);
-    sb.val_a = b.take<uint32_t>(n);
-    sb.val_b = b.take<uint32_t>(n);
-    sb.box_a = b.take<uint32_t>(nb > 1 ? n : 1);
-    sb.box_b = b.take<uint32_t>(nb > 1 ? n : 1);
-    sb.hist = b.take<uint32_t>(2 * 256 * nt);
+    SortBufs sb = carve_sort(b, n, nb);
     int64_t scan_n = n + 1;
     if (256 * nt > scan_n) scan_n = 256 * nt;
     if (mc + 1 > scan_n) scan_n = mc + 1;
@@ -252,6 +296,9 @@ int sfc_ctx_create(sfc_ctx **out, void *hip_stream)
         delete c;
         return SFC_EHIP;
     }
+    // the static scratch of sfc_sort_static on this device (its failure only
+    // disables that call)
+    c->scratch = scratch_resolve(c->device, &c->scratch_err);
     *out = c;
     return SFC_OK;
 }
@@ -336,6 +383,52 @@ int sfc_sort(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out, uint64_t
     ctx->tree_leaf = 0;
     ctx->have_groups = 0;
     ctx->kept_d = ctx->kept_h = 0;
+    return SFC_OK;
+}
+
+int sfc_sort_static(sfc_ctx *ctx, const sfc_particles *in, sfc_particles *out, uint64_t *keys_out,
+                    uint32_t *perm_out)
+{
+    if (!ctx) return SFC_EINVAL;
+    if (!in) return fail(ctx, SFC_EINVAL, "sort_static: particles NULL");
+    if (in->n < 1 || in->n > SFC_SORT_STATIC_MAX_N)
+        return fail(ctx, SFC_EINVAL, "sort_static: n=%lld outside [1, %d] (the static scratch)",
+                    (long long)in->n, SFC_SORT_STATIC_MAX_N);
+    if (in->n_boxes < 1 || in->n_boxes > in->n || in->n_boxes > 65536)
+        return fail(ctx, SFC_EINVAL, "sort_static: n_boxes=%d outside [1, min(n, 65536)]",
+                    in->n_boxes);
+    if (!in->box_off_host || !in->box_off || !in->box_L)
+        return fail(ctx, SFC_EINVAL, "sort_static: box arrays missing");
+    if (in->box_off_host[0] != 0 || in->box_off_host[in->n_boxes] != in->n)
+        return fail(ctx, SFC_EINVAL, "sort_static: box_off must start at 0 and end at n");
+    for (int b = 0; b < in->n_boxes; b++)
+        if (in->box_off_host[b + 1] < in->box_off_host[b])
+            return fail(ctx, SFC_EINVAL, "sort_static: box_off not monotone at %d", b);
+    if (!in->x || !in->y || !in->z || !in->h || !in->m || !in->active)
+        return fail(ctx, SFC_EINVAL, "sort_static: x, y, z, h, m and active are required");
+    if (!out || !keys_out) return fail(ctx, SFC_EINVAL, "sort_static: out and keys_out are required");
+    if (out->n != in->n || !out->x || !out->y || !out->z || !out->h || !out->m || !out->active)
+        return fail(ctx, SFC_EINVAL, "sort_static: out must have n and x, y, z, h, m, active");
+    if (out->x == in->x || out->h == in->h)
+        return fail(ctx, SFC_EINVAL, "sort_static: in and out alias");
+    if (in->orig && !out->orig) return fail(ctx, SFC_EINVAL, "sort_static: out->orig missing");
+    if (!ctx->scratch)
+        return hip_fail(ctx, ctx->scratch_err, "sort_static: no static scratch on this device");
+    // the sort's buffers and its scan scratch, carved from the static array
+    Bump b{(char *)ctx->scratch, 0};
+    SortBufs sb = carve_sort(b, in->n, in->n_boxes);
+    const int64_t nt = (in->n + 4095) / 4096;
+    sb.scan_tmp = b.take<uint32_t>(scan_tmp_elems(256 * nt));
+    if (b.off > (size_t)SFC_STATIC_SCRATCH_BYTES)
+        return fail(ctx, SFC_EINVAL, "sort_static: %zu bytes of scratch needed, %zu held", b.off,
+                    (size_t)SFC_STATIC_SCRATCH_BYTES);
+    hipError_t e = launch_keys(ctx->stream, in, sb);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sort_static keys");
+    uint32_t *perm = nullptr;
+    e = launch_radix_sort(ctx->stream, in->n, in->n_boxes, sb, keys_out, &perm);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sort_static radix sort");
+    e = launch_gather(ctx->stream, in, out, perm, sb.rec, perm_out);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sort_static gather");
     return SFC_OK;
 }
 

@@ -20,11 +20,13 @@ SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_EHIP, SFC_EOVERFLOW, SFC_EORDER = 0, -1,
 POLICY_COUNT, POLICY_PAPER, POLICY_TREE = 0, 1, 2
 KERNEL_CUBIC, KERNEL_WC6 = 0, 1
 ACCUM_F32, ACCUM_F64 = 0, 1
+SORT_STATIC_MAX_N = 262144
 ST_LIST_OVERFLOW, ST_NODE_OVERFLOW, ST_BAD_INPUT, ST_GUARD, ST_REUSE_ACTIVE = 1, 2, 4, 8, 16
 
 EXPORTS = [
     "sfc_ctx_create", "sfc_ctx_destroy", "sfc_ctx_set_stream", "sfc_ctx_last_error",
-    "sfc_ctx_cu_count", "sfc_workspace_bytes", "sfc_workspace_bind", "sfc_sort", "tree_build",
+    "sfc_ctx_cu_count", "sfc_workspace_bytes", "sfc_workspace_bind", "sfc_sort",
+    "sfc_sort_static", "tree_build",
     "tree_refit_hmax", "tree_refit", "group_ngb_search", "density", "hydro_force", "sfc_status_read",
     "sfc_status_clear", "sfc_get_views", "sfc_graph_begin", "sfc_graph_end",
     "sfc_graph_launch", "sfc_graph_destroy",
@@ -135,6 +137,8 @@ def load_library(path: str = LIB_PATH):
     L.sfc_workspace_bind.restype = I
     L.sfc_sort.argtypes = [_P, PP(CParticles), PP(CParticles), _P, _P]
     L.sfc_sort.restype = I
+    L.sfc_sort_static.argtypes = [_P, PP(CParticles), PP(CParticles), _P, _P]
+    L.sfc_sort_static.restype = I
     L.tree_build.argtypes = [_P, PP(CParticles), _P, C.c_int32]
     L.tree_build.restype = I
     L.tree_refit_hmax.argtypes = [_P, PP(CParticles)]
@@ -281,6 +285,13 @@ class Context:
     def sfc_sort(self, pin: Particles, pout: Particles, keys, perm=None):
         a, b = pin.c(), pout.c()
         self._check(self.L.sfc_sort(self.h, C.byref(a), C.byref(b), _ptr(keys), _ptr(perm)))
+
+    def sfc_sort_static(self, pin: Particles, pout: Particles, keys, perm=None):
+        """sfc_sort in the library's static device scratch (no allocation,
+        no workspace needed; n <= SORT_STATIC_MAX_N)."""
+        a, b = pin.c(), pout.c()
+        self._check(self.L.sfc_sort_static(self.h, C.byref(a), C.byref(b), _ptr(keys),
+                                           _ptr(perm)))
 
     def tree_build(self, p: Particles, keys, n_leaf: int):
         a = p.c()
