@@ -49,7 +49,7 @@ def bench_config():
     the 2M lognormal workload)."""
     from paper_1810_09898_amd.pipeline import StepConfig
     from paper_1810_09898_amd import sfcngb as S
-    return StepConfig(n_leaf=128, policy=S.POLICY_PAPER, n_group_max=24, f=0.5, chunk=1024,
+    return StepConfig(n_leaf=128, policy=S.POLICY_PAPER, n_group_max=24, f=0.5,
                       t_cand=2048, hydro_t_cand=2048, skin=1.0)
 
 
@@ -82,15 +82,12 @@ def time_phases(pl, reps=3):
     return {k: float(np.median(v)) for k, v in out.items()}
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The oracle (FP64, OpenMP over targets, cell-grid pruning) on a seeded
-    sample of the same workload: density with the h loop, then hydro."""
+def _oracle_rate(w, s, ob, act, budget_s, seed):
+    """Active updates/s of the oracle on seeded samples of `act` (density with
+    the h loop, then hydro), growing the sample until `budget_s` is used."""
     import oracle
-    ob = oracle.Boxes(w.box_off, w.box_L)
-    keys, perm, s = oracle.sorted_state(w.state, ob)
-    act = np.nonzero(s["active"])[0]
-    rng = np.random.default_rng(0)
-    S = 256
+    rng = np.random.default_rng(seed)
+    S = 64
     t_used = 0.0
     done = 0
     while t_used < budget_s and done < len(act):
@@ -107,11 +104,87 @@ def cpu_baseline(w, budget_s=15.0):
         done += len(samp)
         if dt < budget_s / 8:
             S *= 2
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return done, t_used
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s=15.0, single_s=5.0):
+    """The oracle (FP64, OpenMP over targets, cell-grid pruning) on a seeded
+    sample of the same workload: density with the h loop, then hydro; on
+    every host thread, and on one."""
+    import oracle
+    ob = oracle.Boxes(w.box_off, w.box_L)
+    keys, perm, s = oracle.sorted_state(w.state, ob)
+    act = np.nonzero(s["active"])[0]
+    cores = oracle.get_threads()
+    done, t_used = _oracle_rate(w, s, ob, act, budget_s, 0)
+    oracle.set_threads(1)
+    try:
+        d1, t1 = _oracle_rate(w, s, ob, act, single_s, 1)
+    finally:
+        oracle.set_threads(cores)
     return {"value": done / t_used, "unit": "active updates/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "single_core_value": d1 / t1,
             "sample": f"{done} seeded actives of the 2M lognormal workload, density "
-                      f"(h loop) + hydro, FP64 cell-grid oracle, {t_used:.1f} s"}
+                      f"(h loop) + hydro, FP64 cell-grid oracle, {t_used:.1f} s on {cores} "
+                      f"threads; {d1} actives in {t1:.1f} s on one"}
+
+
+def _stats(e):
+    e = np.asarray(e, np.float64)
+    return {"max": float(e.max()), "p99": float(np.quantile(e, 0.99)),
+            "median": float(np.median(e))}
+
+
+def error_table(w, pl32, pl64, n_samp=2048, seed=7):
+    """Error per field of the GPU step against the FP64 oracle on seeded
+    sampled actives, for the FP32-compensated and the FP64-accumulator
+    variants of the kernels.  Density fields against the oracle's h loop and
+    sums (h must be bit-exact); hydro sums against the oracle's sums on the
+    h, rho and f that the GPU's hydro pass consumed (rho, f stored in FP32).
+    rho and f: relative error; drho/dh, a (each component), du/dt: |error|
+    over the sum of the per-pair term magnitudes; v_sig: relative error."""
+    import oracle
+    ob = oracle.Boxes(w.box_off, w.box_L)
+    keys, perm, s = oracle.sorted_state(w.state, ob)
+    act = np.nonzero(s["active"])[0]
+    rng = np.random.default_rng(seed)
+    samp = np.sort(rng.choice(act, min(n_samp, len(act)), replace=False))
+    r = oracle.density(s["x"], s["y"], s["z"], s["h"], s["m"], ob, samp, w.kernel, w.n_ngb, w.dn,
+                       use_grid=True)
+    out = {"samples": int(len(samp)), "fields": {}}
+    for name, pl, suf in (("fp32_kahan", pl32, ""), ("fp64_accum", pl64, "64")):
+        sn = pl.sorted_numpy(("h", "rho", "fgrad", "orig"))
+        o = pl.outputs_numpy()
+        assert np.array_equal(sn["orig"], s["orig"]), "GPU sort differs from the oracle's"
+        tab = {"h_bit_exact": bool(np.array_equal(sn["h"][samp], r.h))}
+        rho = o["rho64"] if suf else sn["rho"]
+        drho = o["drhodh64"] if suf else o["drhodh"]
+        fg = o["fgrad64"] if suf else sn["fgrad"]
+        tab["rho"] = _stats(np.abs(rho[samp] / r.rho - 1))
+        tab["drhodh"] = _stats(np.abs(drho[samp] - r.drhodh) / r.abs_drhodh)
+        tab["fgrad"] = _stats(np.abs(fg[samp] / r.fgrad - 1))
+        hr = oracle.hydro(s["x"], s["y"], s["z"], sn["h"], s["m"], s["vx"], s["vy"], s["vz"],
+                          s["u"], sn["rho"].astype(np.float64), sn["fgrad"].astype(np.float64),
+                          ob, samp, w.kernel, use_grid=True)
+        ea = np.max([np.abs(o[k + suf][samp] - ref) / hr.abs_a
+                     for k, ref in (("ax", hr.ax), ("ay", hr.ay), ("az", hr.az))], axis=0)
+        tab["acc"] = _stats(ea)
+        tab["dudt"] = _stats(np.abs(o["dudt" + suf][samp] - hr.dudt) / hr.abs_du)
+        tab["vsigmax"] = _stats(np.abs(o["vsigmax"][samp] / hr.vsigmax - 1))
+        out["fields"][name] = tab
+    return out
 
 
 def main():
@@ -121,6 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ungrouped", action="store_true")
+    ap.add_argument("--no-errors", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -184,12 +258,14 @@ def main():
         }
         del ung
 
-    # roofline of the dominant call: density = walk kernel + per-particle
-    # filter/sum kernel; hydro = record kernel + max-h refit + walk kernel +
-    # per-particle kernel.  The calls are bound by vector ALU issue (the
-    # counters show ~65 % VALU issue against ~10 % of HBM), so the roofline is
-    # the ALU one: algorithmic lane instructions (tests and pairs counted by
-    # the kernels x the per-unit costs) / the call's time, against the chip's
+    # roofline of the dominant call (its kernels run back to back on the
+    # library's stream; the events bracket them all): density = record
+    # kernel + walk + group filter rounds + solo members + per-member sums;
+    # hydro = max-h refit + record kernel + walk + group filter + solo
+    # members + per-member sums.  The calls are bound by vector ALU issue and
+    # latency, not by HBM bandwidth, so the roofline is the ALU one:
+    # algorithmic lane instructions (tests and pairs counted by the kernels x
+    # the per-unit costs) / the call's time, against the chip's
     # lane-instruction rate.  The HBM view (algorithmic bytes) rides along.
     dens_bytes = st_d["sum_cand"] * DENS_BC + A * DENS_BIO
     hyd_bytes = st_h["sum_cand"] * HYD_BC + A * HYD_BIO
@@ -216,8 +292,9 @@ def main():
     roof = {"bound": "alu", "achieved": round(ach_ops, 3), "peak": round(peak_t, 2),
             "unit": "T lane-instructions/s", "frac": round(ach_ops / peak_t, 4),
             "traffic": traffic, "kernel": kname,
-            "kernels": ("k_walk + k_density" if kname == "density"
-                        else "k_hydro_prep + refit + k_walk + k_hydro"),
+            "kernels": ("k_dens_prep + k_walk + k_dgroup + k_dens_solo + k_dsum"
+                        if kname == "density"
+                        else "refit + k_hydro_prep + k_walk + k_hgroup + k_hydro_solo + k_hsum"),
             "algorithmic_ops": int(kops),
             "ops_model": f"{TEST_OPS} per member x candidate test, {DENS_PAIR_OPS} per density "
                          f"pair, {HYD_PAIR_OPS} per hydro pair",
@@ -230,6 +307,17 @@ def main():
                                              / ((ph["hydro"] if kname == "density" else ph["density"])
                                                 * 1e-3) / ALU_PEAK_LANE_OPS, 4)},
             "valu": valu}
+
+    # error per field against the FP64 oracle (both accumulators)
+    err = None
+    if not args.no_errors:
+        pl64 = Pipeline(w, cfg.with_(accum=S.ACCUM_F64))
+        pl.step()
+        pl64.step()
+        torch.cuda.synchronize()
+        err = error_table(w, pl, pl64)
+        del pl64
+        print(f"# error table done", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -266,6 +354,7 @@ def main():
         "h_evaluations_per_active": round(st_d["sum_iters"] / A, 3),
         "solo_members": st_d["n_deferred"] + st_h["n_deferred"],
         "roofline": roof,
+        "error_vs_fp64_oracle": err,
         "cpu_baseline": cpu,
         "paper_speedups_context": {"density": 1.65, "hydro": 1.30, "total": 1.34,
                                    "hardware": "Gadget3 on 8 MPI ranks x 2 threads (CPU)"},

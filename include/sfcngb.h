@@ -165,7 +165,6 @@ typedef struct {
     int32_t n_group_max; /* 1..64 members per group */
     double f;            /* paper policy: a particle joins while closer than f*h_0 to the
                             group's first member (section "Adaptive Neighbour Recycling") */
-    int32_t chunk;       /* the greedy scan restarts every `chunk` actives of a box (>= 64) */
     int32_t level;       /* tree policy (0..21): a particle joins while it lies in the octree
                             node of depth `level` that holds the group's first member, or, when
                             that member's leaf is shallower, in that leaf (section "Neighbour
@@ -192,10 +191,12 @@ typedef struct {
 } sfc_verify;
 
 /* Active list (curve order) and groups (section "Implementation of
- * Neighbour Recycling using a Space Filling Curve"): the first active opens
- * a group, the next active joins while the policy allows, otherwise it opens
- * the next group; a box boundary and every `chunk`-th active of a box also
- * open a group.  gp: host pointer to one parameter set used for every box,
+ * Neighbour Recycling using a Space Filling Curve"): one greedy pass over
+ * the actives in curve order, as the paper runs it: the first active opens
+ * a group, the next active joins while the policy allows and the group has
+ * fewer than n_group_max members, otherwise it opens the next group; a box
+ * boundary also opens a group.  (Computed in parallel; the groups are those
+ * of the sequential pass exactly.)  gp: host pointer to one parameter set used for every box,
  * or NULL when gp_box is given.  gp_box: device [n_boxes] per-box parameters
  * or NULL.  With verify != NULL the walk and filter run once for every group
  * and write the neighbour sets (no physics); t_cand is the candidate tile
@@ -253,8 +254,8 @@ typedef struct {
  * SFC_ST_REUSE_ACTIVE.  Results are those of a walking call.  sfc_sort,
  * tree_build and group_ngb_search drop the kept supersets.
  * The particle arrays are the ones the walking call saw, in the same order
- * (moved in place by the caller).  hydro_force with reuse = 1 refits the
- * node boxes itself; density needs tree_refit first.  Errors (host side,
+ * (moved in place by the caller).  density and hydro_force with reuse = 1
+ * refit the node boxes themselves (tree_refit).  Errors (host side,
  * nothing enqueued): SFC_EORDER when no superset is kept, SFC_EINVAL for a
  * t_cand other than the walking call's.  keep_supersets enlarges the
  * workspace (a second candidate buffer and group records, snapshots);

@@ -58,6 +58,10 @@ _I32, _I64, _D, _U32 = C.c_int32, C.c_int64, C.c_double, C.c_uint32
 
 
 def _declare(L):
+    L.orc_set_threads.restype = None
+    L.orc_set_threads.argtypes = [_I32]
+    L.orc_get_threads.restype = _I32
+    L.orc_get_threads.argtypes = []
     L.orc_hilbert_key_cell.restype = C.c_uint64
     L.orc_hilbert_key_cell.argtypes = [_U32, _U32, _U32, _I32]
     L.orc_hilbert_keys.restype = None
@@ -66,8 +70,7 @@ def _declare(L):
     L.orc_octree.argtypes = [_I64, _P, _I32, _P, _I32, _I32, _P, _P, _P, _P, _I64,
                              _P, _P, _P, _P, _P, _P, _P]
     L.orc_groups.restype = _I64
-    L.orc_groups.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _I32,
-                             _P]
+    L.orc_groups.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _P]
     L.orc_ngb_count.restype = None
     L.orc_ngb_count.argtypes = [_I32, _I64, _P, _P, _P, _P, _P, _I32, _P, _P, _I64, _P,
                                 _I32, _P, _P]
@@ -90,6 +93,15 @@ def _declare(L):
     L.orc_group_superset_size.restype = _I64
     L.orc_group_superset_size.argtypes = [_I64, _P, _P, _P, _P, _I32, _P, _P, _P, _I64,
                                           _I64, _D]
+
+
+def set_threads(n: int) -> None:
+    """Threads of the OpenMP loops over targets."""
+    _lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_lib().orc_get_threads())
 
 
 def _c(a, dtype):
@@ -215,11 +227,13 @@ def leaf_levels(tree: Tree, n: int) -> np.ndarray:
     return out
 
 
-def groups(act, x, y, z, h, boxes: Boxes, policy, n_group_max, f, chunk: int, level=0,
+def groups(act, x, y, z, h, boxes: Boxes, policy, n_group_max, f, level=0,
            leaf_level=None) -> np.ndarray:
     """Group starts (positions in `act`, plus A at the end) of the greedy
-    grouping along the curve; policy/n_group_max/f/level scalar or per box.
-    The tree policy needs leaf_level (leaf_levels() of the octree)."""
+    grouping along the curve, one pass over the whole active list (section
+    "Implementation of Neighbour Recycling using a Space Filling Curve");
+    policy/n_group_max/f/level scalar or per box.  The tree policy needs
+    leaf_level (leaf_levels() of the octree)."""
     act = _c(act, np.int32)
     x, y, z, h = (_c(a, np.float64) for a in (x, y, z, h))
     box = _c(boxes.box_of(), np.int32)
@@ -234,7 +248,7 @@ def groups(act, x, y, z, h, boxes: Boxes, policy, n_group_max, f, chunk: int, le
     out = np.empty(len(act) + 1, np.int32)
     G = _lib().orc_groups(len(act), _ptr(act), _ptr(x), _ptr(y), _ptr(z), _ptr(h),
                           _ptr(box), _ptr(_c(boxes.L, np.float64)), _ptr(pol), _ptr(cap),
-                          _ptr(ff), chunk, _ptr(lev), _ptr(ll), KEY_BITS, _ptr(out))
+                          _ptr(ff), _ptr(lev), _ptr(ll), KEY_BITS, _ptr(out))
     return out[:G + 1].copy()
 
 

@@ -25,11 +25,16 @@
  * listed in the design notes.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
+
+/* threads of the OpenMP loops over targets (timing on one core or all) */
+void orc_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+int32_t orc_get_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* Periodic minimum-image displacement (READING: the test box is a     */
@@ -206,12 +211,12 @@ int64_t orc_octree(int64_t n, const uint64_t *key, int32_t nbox, const int64_t *
 /* Space Filling Curve"): walk the active particles in curve order;    */
 /* the first one opens a group; each next one joins while it is closer */
 /* than R to the group's first particle; the first one that is not     */
-/* opens the next group.  R = f h_0 (section "Adaptive Neighbour       */
+/* opens the next group, until no particle is left: one pass over the  */
+/* whole active list.  R = f h_0 (section "Adaptive Neighbour          */
 /* Recycling"), READING h_0 = h of the group's first particle, strict  */
 /* "<".  Additional closing rules (READINGS): a group never crosses a  */
-/* box, never exceeds n_group_max members, and the scan restarts every */
-/* `chunk` actives of a box (each worker walks its own slice of the    */
-/* active list).  policy 0 ("count") drops the distance test.          */
+/* box and never exceeds n_group_max members.                          */
+/* policy 0 ("count") drops the distance test.                         */
 /* policy 2 ("tree", section "Adaptive Neighbour Recycling": a group   */
 /* is the set of leaves inside a node of one tree depth): a particle   */
 /* joins while it lies in the same octree node as the group's first    */
@@ -225,25 +230,21 @@ int64_t orc_octree(int64_t n, const uint64_t *key, int32_t nbox, const int64_t *
 int64_t orc_groups(int64_t A, const int32_t *act, const double *x, const double *y,
                    const double *z, const double *h, const int32_t *box,
                    const double *box_L, const int32_t *policy, const int32_t *n_group_max,
-                   const double *f, int64_t chunk, const int32_t *level,
+                   const double *f, const int32_t *level,
                    const int32_t *leaf_level, int32_t bits, int32_t *gstart)
 {
     int64_t G = 0;
-    int64_t k0 = -1, size = 0, box_first = 0;
+    int64_t k0 = -1, size = 0;
     for (int64_t k = 0; k < A; k++) {
         int32_t i = act[k];
         int32_t b = box ? box[i] : 0;
         int open = 0;
         if (k0 < 0) {
             open = 1;
-            box_first = k;
         } else {
             int32_t i0 = act[k0];
             int32_t b0 = box ? box[i0] : 0;
             if (b != b0) {
-                open = 1;
-                box_first = k;
-            } else if (chunk > 0 && (k - box_first) % chunk == 0) {
                 open = 1;
             } else if (size >= n_group_max[b]) {
                 open = 1;

@@ -114,8 +114,6 @@ int64_t node_capacity(const sfc_dims &d)
     return d.n + 22 * d.n / ((int64_t)d.n_leaf_min + 1) + d.n_boxes + 64;
 }
 
-int64_t max_chunks(const sfc_dims &d) { return d.n / 64 + d.n_boxes + 1; }
-
 int64_t sort_tiles(const sfc_dims &d) { return (d.n + 4095) / 4096; }
 
 int64_t cand_capacity(const sfc_dims &d)
@@ -155,13 +153,12 @@ bool dims_ok(const sfc_dims *d)
 size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
 {
     Bump b{base, 0};
-    int64_t n = d.n, nb = d.n_boxes, cap = node_capacity(d), mc = max_chunks(d);
+    int64_t n = d.n, nb = d.n_boxes, cap = node_capacity(d);
     int64_t nt = sort_tiles(d);
     DevStatus *st = b.take<DevStatus>(1);
     SortBufs sb = carve_sort(b, n, nb);
     int64_t scan_n = n + 1;
     if (256 * nt > scan_n) scan_n = 256 * nt;
-    if (mc + 1 > scan_n) scan_n = mc + 1;
     uint32_t *scan_tmp = b.take<uint32_t>(scan_tmp_elems(scan_n));
     sb.scan_tmp = scan_tmp;
     TreeBufs tb;
@@ -181,14 +178,19 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     GroupBufs gb;
     gb.flag_scan = b.take<uint32_t>(n + 1);
     gb.act = b.take<int32_t>(n);
-    gb.chunk_base = b.take<int32_t>(nb + 1);
-    gb.gs_local = b.take<int32_t>(n);
-    gb.gcount = b.take<uint32_t>(mc + 1);
-    gb.gscan = b.take<uint32_t>(mc + 1);
+    gb.nxt = b.take<int32_t>(n);
+    {
+        int64_t ni[GROUP_LEVELS_MAX], sp[GROUP_LEVELS_MAX];
+        const int L = group_levels(n, ni, sp);
+        for (int l = 0; l < GROUP_LEVELS_MAX; l++) {
+            gb.map[l] = l < L ? b.take<GMap>(ni[l]) : nullptr;
+            gb.ent[l] = l < L ? b.take<int32_t>(ni[l]) : nullptr;
+            gb.before[l] = l < L ? b.take<int32_t>(ni[l]) : nullptr;
+        }
+    }
     gb.goff = b.take<int32_t>(n + 1);
     gb.n_act = b.take<int32_t>(1);
     gb.n_groups = b.take<int32_t>(1);
-    gb.max_chunks = mc;
     SearchBufs xb;
     xb.cand_cap = cand_capacity(d);
     xb.cand = b.take<int32_t>(xb.cand_cap);
@@ -197,6 +199,10 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     xb.pa = b.take<float4>(n);
     xb.pb = b.take<float4>(n);
     xb.pos4 = b.take<float4>(n);
+    xb.p64 = b.take<double4>(n);
+    xb.dstate = b.take<double4>(n);
+    xb.gmask = b.take<uint64_t>(n * (int64_t)(d.t_cand_max / 64));
+    xb.gflag = b.take<uint8_t>(n);
     xb.snap = nullptr;
     xb.drift = nullptr;
     xb.sel = nullptr;
@@ -484,7 +490,6 @@ static int check_group_params(sfc_ctx *ctx, const sfc_group_params *gp)
         return fail(ctx, SFC_EINVAL, "group params: n_group_max %d outside [1, 64]", gp->n_group_max);
     if (gp->policy == SFC_POLICY_PAPER && !(gp->f >= 0.0))
         return fail(ctx, SFC_EINVAL, "group params: f must be >= 0");
-    if (gp->chunk < 64) return fail(ctx, SFC_EINVAL, "group params: chunk must be >= 64");
     return SFC_OK;
 }
 
@@ -558,7 +563,14 @@ int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp, sfc_de
     if (out) a.out = *out;
     else memset(&a.out, 0, sizeof(a.out));
     PartDev pd = part_dev(p);
-    hipError_t e = launch_density(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
+    hipError_t e = hipSuccess;
+    if (dp->reuse) {
+        // members that leave a kept superset walk the tree: its node boxes
+        // must span the particles where they are now
+        e = launch_tree_refit(ctx->stream, pd, ctx->td, true, ctx->st, p->n);
+        if (e != hipSuccess) return hip_fail(ctx, e, "density refit");
+    }
+    e = launch_density(ctx->stream, pd, ctx->td, ctx->gb, ctx->xb, a, ctx->st);
     if (e != hipSuccess) return hip_fail(ctx, e, "density");
     if (a.keep) ctx->kept_d = dp->t_cand;
     return SFC_OK;

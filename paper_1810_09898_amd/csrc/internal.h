@@ -140,7 +140,8 @@ struct DevStatus {
     // serialise on one address: bump pointers of the eight regions of the
     // candidate buffer and the walk kernel's work counters.
     unsigned long long cand_top[8 * 16]; // cand_top[16 * x]
-    int32_t qctr[8 * 32];                // qctr[32 * x]
+    int32_t qctr[8 * 32];                // qctr[32 * x]: the walk kernel's
+    int32_t qctr2[8 * 32];               // qctr2[32 * x]: the group kernels'
 };
 
 // per-group record written by the walk kernel
@@ -232,18 +233,29 @@ hipError_t launch_tree_build(hipStream_t s, const PartDev &p, const uint64_t *ke
 hipError_t launch_tree_refit(hipStream_t s, const PartDev &p, TreeDev &t, bool bbox,
                              DevStatus *st, int64_t n);
 
+// Grouping: per active the position that would open the next group, and
+// per block of the active list (GB1 = 1024 positions at level 0, 64 times
+// more per level above) the map of the orbit through it, its true entry
+// and the number of groups before it.
+#define GROUP_LEVELS_MAX 6
+struct GMap {
+    int32_t exit[64]; // entry e (the block's position e) -> where the orbit leaves the block
+    int32_t cnt[64];  // -> group starts on the way
+};
 struct GroupBufs {
     uint32_t *flag_scan; // [n+1] exclusive scan of active flags
     int32_t *act;        // [n]
-    int32_t *chunk_base; // [nb+1]
-    int32_t *gs_local;   // [n] group starts per chunk (chunk-local slots)
-    uint32_t *gcount;    // [max_chunks+1]
-    uint32_t *gscan;     // [max_chunks+1]
+    int32_t *nxt;        // [n]
+    GMap *map[GROUP_LEVELS_MAX];
+    int32_t *ent[GROUP_LEVELS_MAX];
+    int32_t *before[GROUP_LEVELS_MAX];
     int32_t *goff;       // [n+1]
     int32_t *n_act;      // device scalar
     int32_t *n_groups;   // device scalar
-    int64_t max_chunks;
 };
+// items and span (positions) of each level of the maps for n actives at most;
+// returns the number of levels
+int group_levels(int64_t n, int64_t *n_items, int64_t *span);
 hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params *gp,
                          const sfc_group_params *gp_box, const int8_t *dlev, GroupBufs &g,
                          uint32_t *scan_tmp, DevStatus *st);
@@ -254,7 +266,13 @@ struct SearchBufs {
     GSup *sup;        // [n] per group
     int32_t *grp;     // [n] per active: its group
     float4 *pa, *pb;  // [n] hydro records: (m, v) and (rho, f P / rho^2, c, h)
-    float4 *pos4;     // [n] density: FP32 x, y, z and m
+    float4 *pos4;     // [n] FP32 x, y, z and (density) m or (hydro) h, for the walks
+    double4 *p64;     // [n] FP64 x, y, z, h: the group filters and the pair terms
+    double4 *dstate;  // [n] per active: h, bracket lo, hi, evaluations (members that leave
+                      // their group superset)
+    uint64_t *gmask;  // [n * t_cand_max / 64] per active: its neighbour masks over its
+                      // group's candidate chunks (written by the group kernels)
+    uint8_t *gflag;   // [n] per active: 1 = its group computed it (sums from gmask)
     double4 *snap;    // [n] kept supersets: x, y, z (and h) when they were walked, or NULL
     unsigned long long *drift; // [4 + 3 * 512] largest displacement, largest h growth since
                                // (FP64 bits), active particles now, members active now;

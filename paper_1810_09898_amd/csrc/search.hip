@@ -81,6 +81,43 @@ template <int KER, typename T> __device__ __forceinline__ void kern_eval(T q, T 
     }
 }
 
+// the same from q and an accurate u = 1 - q (0 outside the support): the
+// pair terms form u as (h^2 - r^2) / (h^2 (1 + q)) with the difference taken
+// in FP64, so the tail (1 - q)^k keeps its relative accuracy up to the edge
+template <int KER, typename T> __device__ __forceinline__ void kern_eval_u(T q, T u, T &w, T &dw)
+{
+    if (KER == 0) {
+        T wo = T(2) * u * u * u;
+        T dwo = T(-6) * u * u;
+        T wi = mad(q * q, mad(T(6), q, T(-6)), T(1));
+        T dwi = q * mad(T(18), q, T(-12));
+        bool inner = q < T(0.5);
+        w = inner ? wi : wo;
+        dw = inner ? dwi : dwo;
+    } else {
+        T u2 = u * u, u4 = u2 * u2, u7 = u4 * u2 * u, u8 = u4 * u4;
+        w = u8 * mad(q, mad(q, mad(T(32), q, T(25)), T(8)), T(1));
+        dw = T(-22) * q * u7 * mad(q, mad(T(16), q, T(7)), T(1));
+    }
+}
+
+// 1 - q for q = sqrt(r2) / h, from the FP64 r2 and h2 = h^2: the difference
+// h2 - r2 is exact near the edge (the two are within a factor 2), so the
+// result has a small relative error even where it is tiny; 0 outside
+template <typename T> __device__ __forceinline__ T tail_u(double h2, double r2, T inv_h2, T q);
+template <> __device__ __forceinline__ float tail_u<float>(double h2, double r2, float inv_h2, float q)
+{
+    const double dd = h2 - r2;
+    return dd > 0.0 ? (float)dd * inv_h2 * __builtin_amdgcn_rcpf(1.0f + q) : 0.0f;
+}
+template <> __device__ __forceinline__ double tail_u<double>(double h2, double r2, double inv_h2, double q)
+{
+    (void)h2;
+    (void)r2;
+    (void)inv_h2;
+    return q < 1.0 ? 1.0 - q : 0.0;
+}
+
 template <typename T> struct Kahan {
     T s = T(0), c = T(0);
     __device__ __forceinline__ void add(T v)
@@ -561,18 +598,53 @@ __device__ __forceinline__ double r2_of(double xj, double yj, double zj, double 
 // records whether a kept candidate needed the periodic fold relative to the
 // centre and the largest per-axis displacement of a kept candidate
 // (lane-wise, see pair_wrap).
+// The walk kernel's chunk of the candidate buffer, [cur, end): a superset
+// starts in what is left of it and, when it outgrows that, moves to a fresh
+// chunk (what it wrote so far is copied), so that no group leaves a tile's
+// worth of slots unused behind it.
+struct CandChunk {
+    DevStatus *st;
+    int32_t *cand; // the whole buffer
+    int64_t cap;   // its capacity
+    int64_t cur, end;
+    int size;      // slots of a fresh chunk (>= T)
+    int x;         // XCD of the wave: its region of the buffer first
+};
+
+// Bump allocation of cnt candidates in region x (of 8) of the candidate
+// buffer; -1 when every region is full.
+__device__ __forceinline__ int64_t cand_alloc(DevStatus *st, int64_t cap, int x, int cnt)
+{
+    const int64_t rcap = cap >> 3;
+    // the own region first, then the others: a region fills up before the
+    // rest where its XCD took more than its share of the work
+#pragma unroll 1
+    for (int t = 0; t < 8; t++) {
+        const int r = (x + t) & 7;
+        unsigned long long off = 0ull;
+        if (lane_id() == 0) off = atomicAdd(&st->cand_top[16 * r], (unsigned long long)cnt);
+        off = uni_u64(off);
+        if ((int64_t)off + cnt <= rcap) return (int64_t)r * rcap + (int64_t)off;
+    }
+    return -1;
+}
+
 struct AppendCand {
     const float4 *p4; // x, y, z and, for hydro, h in FP32
     int *cand;
-    int T;
+    int T;            // most candidates a superset may hold
+    int room;         // slots at cand (<= T)
     int n;
     bool over;
     bool folded;
     Ball B;
     double ext;
+    CandChunk *ck;    // the walk's chunk (grows into a fresh one), or NULL: room is all
     float cx, cy, cz, L, Rg, Hg, w2; // w2: widened density limit
-    __device__ AppendCand(const float4 *p4_, int *cand_, int T_, const Ball &B_, double ext_)
-        : p4(p4_), cand(cand_), T(T_), n(0), over(false), folded(false), B(B_), ext(ext_)
+    __device__ AppendCand(const float4 *p4_, int *cand_, int T_, const Ball &B_, double ext_,
+                          int room_ = -1, CandChunk *ck_ = nullptr)
+        : p4(p4_), cand(cand_), T(T_), room(room_ < 0 ? T_ : room_), n(0), over(false),
+          folded(false), B(B_), ext(ext_), ck(ck_)
     {
         cx = (float)B.cx;
         cy = (float)B.cy;
@@ -614,12 +686,32 @@ struct AppendCand {
         const uint64_t m = ballot(keep);
         if (ballot(keep && fl)) folded = true;
         const int cnt = popc64(m);
-        if (n + cnt > T) {
-            over = true;
-            return;
+        if (n + cnt > room) {
+            if (n + cnt > T || !ck || !grow()) {
+                over = true;
+                return;
+            }
         }
         if (keep) cand[n + mbcnt(m)] = j;
         n = uni(n + cnt);
+    }
+    // move the superset to a fresh chunk of the buffer (room becomes T)
+    __device__ bool grow()
+    {
+        const int64_t base = cand_alloc(ck->st, ck->cap, ck->x, ck->size);
+        if (base < 0) {
+            ck->cur = ck->end = -1;
+            return false;
+        }
+        int *dst = ck->cand + base;
+        // this wave wrote the first n entries: order them before the reads
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        for (int t = lane_id(); t < n; t += 64) dst[t] = cand[t];
+        cand = dst;
+        room = T;
+        ck->cur = base;
+        ck->end = base + ck->size;
+        return true;
     }
 };
 
@@ -649,24 +741,6 @@ __device__ __forceinline__ BoxInfo box_info(const Geom &geo, int i)
     return bi;
 }
 
-// Bump allocation of cnt candidates in region x (of 8) of the candidate
-// buffer; -1 when the region is full.
-__device__ __forceinline__ int64_t cand_alloc(DevStatus *st, const CandArg &ca, int x, int cnt)
-{
-    const int64_t rcap = ca.cap >> 3;
-    // the own region first, then the others: a region fills up before the
-    // rest where its XCD took more than its share of the work
-#pragma unroll 1
-    for (int t = 0; t < 8; t++) {
-        const int r = (x + t) & 7;
-        unsigned long long off = 0ull;
-        if (lane_id() == 0) off = atomicAdd(&st->cand_top[16 * r], (unsigned long long)cnt);
-        off = uni_u64(off);
-        if ((int64_t)off + cnt <= rcap) return (int64_t)r * rcap + (int64_t)off;
-    }
-    return -1;
-}
-
 } // namespace
 
 // ================================================================== walk kernel
@@ -689,6 +763,7 @@ __global__ void k_reset_pass(DevStatus *st)
     if (t < 8) {
         st->cand_top[16 * t] = 0ull;
         st->qctr[32 * t] = 0;
+        st->qctr2[32 * t] = 0;
     }
     if (t == 8) st->n_dfr = 0ull;
 }
@@ -749,9 +824,14 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     Queue wq = queue_open(k.st->qctr, G);
     WaveStats ws;
     // candidates are placed in chunks taken by this wave: up to 8192 slots,
-    // at most a quarter of a wave's fair share of the buffer
-    const int CHUNK = (int)max((int64_t)64, min((int64_t)8192, k.ca.cap / (4 * (int64_t)gridDim.x)));
-    int64_t ck_cur = 0, ck_end = 0;
+    // at most a quarter of a wave's fair share of the buffer, at least a tile
+    CandChunk ck;
+    ck.st = k.st;
+    ck.cand = k.ca.cand;
+    ck.cap = k.ca.cap;
+    ck.size = (int)max((int64_t)T, min((int64_t)8192, k.ca.cap / (4 * (int64_t)gridDim.x)));
+    ck.x = blockIdx.x & 7;
+    ck.cur = ck.end = 0;
     for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
         const int a = uni(k.ga.goff[g]);
         const int nm = min(uni(k.ga.goff[g + 1]) - a, 64);
@@ -788,31 +868,31 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         const int nowrap = cx - rad >= 0.0 && cx + rad < bx.L && cy - rad >= 0.0 &&
                            cy + rad < bx.L && cz - rad >= 0.0 && cz + rad < bx.L;
         Ball B{cx, cy, cz, bx.L, sq(cov * INFL), Rs, H, k.hydro, nowrap};
-        // the superset goes straight to the wave's current chunk of the
-        // buffer, which must hold a full tile (a new chunk otherwise; the
-        // rest of the old one stays unused)
-        if (ck_cur >= 0 && ck_end - ck_cur < T) {
-            const int csz = max(T, CHUNK);
-            const int64_t base = cand_alloc(k.st, k.ca, blockIdx.x & 7, csz);
-            ck_cur = base;
-            ck_end = base < 0 ? base : base + csz;
+        // the superset goes straight to what is left of the wave's current
+        // chunk of the buffer (a fresh chunk when that is nearly used up;
+        // a superset that outgrows it moves to a fresh one)
+        if (ck.cur >= 0 && ck.end - ck.cur < 64) {
+            const int64_t base = cand_alloc(k.st, k.ca.cap, ck.x, ck.size);
+            ck.cur = base;
+            ck.end = base < 0 ? base : base + ck.size;
         }
         int flags = 0;
         int64_t c0 = 0;
         int nc = 0;
-        const bool walked = ck_cur >= 0;
+        const bool walked = ck.cur >= 0;
         if (!walked) { // the buffer is used up: the members walk on their own
             flags = GSUP_SOLO;
         } else {
-            AppendCand ap(k.pos4, k.ca.cand + ck_cur, T, B, nowrap ? rad : 0.0);
+            AppendCand ap(k.pos4, k.ca.cand + ck.cur, T, B, nowrap ? rad : 0.0,
+                          (int)min((int64_t)T, ck.end - ck.cur), &ck);
             if (!walk_levels(k.g, bx.root, B, lst, lst + LCAP, lst + 2 * LCAP, ap)) // list too long: window walk
                 walk(k.g, bx.root, bx.root_end, B, ap, k.st);
             nc = uni(ap.n);
             if (uni_b(ap.over)) {
                 flags = GSUP_SOLO;
             } else {
-                c0 = ck_cur;
-                ck_cur += nc;
+                c0 = ck.cur;
+                ck.cur += nc;
                 if (pair_wrap(uni_b(ap.folded), ap.ext, mfold, mext, bx.L)) flags |= GSUP_WRAP;
             }
         }
@@ -842,13 +922,14 @@ namespace {
 // ------------------------------------------------------------------ per-member set-up
 constexpr int FIFO_B = 4; // neighbour batches of 64 consumed together
 
-// LDS of one member wave: neighbour masks of the last filter pass, the FIFO
-// and the squared-distance cache
+// LDS of one member wave (the passes of members that walk alone):
+// neighbour masks of the last filter pass, the FIFO and the squared-distance
+// cache of the count passes.
 // squared distances kept (as FP32) for the first R2C_MAX candidates
 constexpr int R2C_MAX = 1024;
 __host__ __device__ constexpr int r2c_len(int T, bool cache) { return cache ? (T < R2C_MAX ? T : R2C_MAX) : 0; }
 
-constexpr int FIFO_BYTES = 64 * 3 * 16; // the larger of 64*(FIFO_B+1) density and 64*3 hydro entries
+constexpr int FIFO_BYTES = 64 * (FIFO_B + 1) * 4; // the larger FIFO (density: FIFO_B + 1 batches of ints)
 
 struct MemLds {
     uint64_t *masks; // [T/64]
@@ -879,21 +960,26 @@ struct Member {
     GSup s;
     BoxInfo bx;
 };
+__device__ __forceinline__ GSup load_gsup(const GSup *sp)
+{
+    GSup s;
+    s.cx = uni_d(sp->cx);
+    s.cy = uni_d(sp->cy);
+    s.cz = uni_d(sp->cz);
+    s.cov = uni_d(sp->cov);
+    s.rs = uni_d(sp->rs);
+    const int64_t c0 = sp->c0;
+    s.c0 = ((int64_t)uni((int)(c0 >> 32)) << 32) | (uint32_t)uni((int)(uint32_t)c0);
+    s.nc = uni(sp->nc);
+    s.flags = uni(sp->flags);
+    return s;
+}
 __device__ __forceinline__ Member member(const Geom &geo, const GroupArg &ga, const CandArg &ca, int a)
 {
     Member M;
     M.i = uni(ga.act[a]);
     M.g = uni(ca.grp[a]);
-    const GSup *sp = ca.sup + M.g;
-    M.s.cx = uni_d(sp->cx);
-    M.s.cy = uni_d(sp->cy);
-    M.s.cz = uni_d(sp->cz);
-    M.s.cov = uni_d(sp->cov);
-    M.s.rs = uni_d(sp->rs);
-    const int64_t c0 = sp->c0;
-    M.s.c0 = ((int64_t)uni((int)(c0 >> 32)) << 32) | (uint32_t)uni((int)(uint32_t)c0);
-    M.s.nc = uni(sp->nc);
-    M.s.flags = uni(sp->flags);
+    M.s = load_gsup(ca.sup + M.g);
     M.bx = box_info(geo, M.i);
     M.xi = uni_d(geo.x[M.i]);
     M.yi = uni_d(geo.y[M.i]);
@@ -919,18 +1005,16 @@ __device__ __forceinline__ void solo_walk(const Geom &g, const MemLds &S, const 
     walk(g, M.bx.root, M.bx.root_end, B, visit, st);
 }
 
-// FIFO entries: a neighbour and what the filter already knows of the pair.
-// Density: the FP32 r^2 of the FP32 positions (r2_f32).  Hydro: the
-// minimum-image x_i - x_j of the FP32 positions.  Every path that pushes a pair
-// computes these the same way, so a particle's sums do not depend on the
-// path (group superset, own superset or own walk).
+// FIFO entries: a neighbour.  The pair's values (r^2 for density, the
+// displacement for hydro) are formed when its term is computed, from the
+// FP64 positions of the two particles only, so a particle's sums do not
+// depend on the path that found the pair (group superset, own superset or
+// own walk) nor on the group it was in.
 struct DEnt {
     int j;
-    float r2;
 };
 struct HEnt {
     int j;
-    float dx, dy, dz;
 };
 
 // FIFO of neighbour entries; the k-th pushed entry is consumed by lane k%64.
@@ -953,7 +1037,7 @@ template <int B, class E> struct FifoB {
         for (int b = 0; b < B; b++) {
             const int idx = (b << 6) + lane;
             v[b] = idx < cnt;
-            if ((b << 6) < cnt) t[b] = f.term(v[b] ? buf[wrap(head + idx)] : E{});
+            if ((b << 6) < cnt) t[b] = f.term(v[b] ? buf[wrap(head + idx)] : E{0});
         }
 #pragma unroll
         for (int b = 0; b < B; b++)
@@ -984,12 +1068,13 @@ template <int B, class E> struct FifoB {
 };
 typedef FifoB<FIFO_B, DEnt> Fifo;
 typedef FifoB<2, HEnt> FifoH; // hydro terms are larger: two batches at a time
+static_assert(FifoB<FIFO_B, DEnt>::SIZE * sizeof(DEnt) <= FIFO_BYTES, "density FIFO fits");
+static_assert(FifoB<2, HEnt>::SIZE * sizeof(HEnt) <= FIFO_BYTES, "hydro FIFO fits");
 
 constexpr int UNR = 4; // candidate chunks loaded together
 
 // Pair r^2 in FP32 from the FP32 copies of the positions (rounded to
-// nearest), folded in FP32 when `wrap`.  Every path that needs a pair's FP32
-// r^2 computes it this way, so the density sums see one value per pair.
+// nearest), folded in FP32 when `wrap`: the screen of the count passes.
 __device__ __forceinline__ float r2_f32(float xj, float yj, float zj, float xi, float yi, float zi,
                                         float L, bool wrap)
 {
@@ -1002,14 +1087,15 @@ __device__ __forceinline__ float r2_f32(float xj, float yj, float zj, float xi, 
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
-// density count pass over the group superset: masks of r2 < h2, their count.
-// The test is decided on the FP32 r^2 of the FP32 positions wherever that is
-// safely away from h^2, and on the canonical FP64 r^2 otherwise, so the
-// result is exactly that of the FP64 test.  Bound: each coordinate is off by
-// at most u L (u = 2^-24, coordinates in [0, L)), a (folded) difference by
-// 4 u L + u |d|, so near r = h the FP32 r^2 is within 14 u L h + 5 u h^2 of
-// the FP64 one; the band is E = 16 u (L h + h^2).  The first pass keeps the
-// FP32 r^2 of the first S.rc candidates in LDS for the later passes.
+// density count pass over a member's own superset: masks of r2 < h2, their
+// count.  The test is decided on the FP32 r^2 of the FP32 positions wherever
+// that is safely away from h^2, and on the canonical FP64 r^2 otherwise, so
+// the result is exactly that of the FP64 test.  Bound: each coordinate is
+// off by at most u L (u = 2^-24, coordinates in [0, L)), a (folded)
+// difference by 4 u L + u |d|, so near r = h the FP32 r^2 is within
+// 14 u L h + 5 u h^2 of the FP64 one; the band is E = 16 u (L h + h^2).  The
+// first pass keeps the FP32 r^2 of the first S.rc candidates in LDS for the
+// later passes.
 __device__ __forceinline__ int count_pass(const Geom &geo, const float4 *P, const int32_t *cand,
                                           const Member &M, double h, bool wrap, const MemLds &S,
                                           bool first)
@@ -1043,10 +1129,6 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const float4 *P, cons
         if (lane == 0) S.masks[c] = hm;
         cnt += popc64(hm);
     }
-    // the rest: UNR chunks per step, all their loads issued before the tests,
-    // and the candidate indices of the next step loaded while this one is
-    // tested (loads are unconditional, on clamped slots, so they go out
-    // together)
     int jn[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; u++) jn[u] = cg[min(((cached + u) << 6) + lane, nc - 1)];
@@ -1087,36 +1169,24 @@ __device__ __forceinline__ int count_pass(const Geom &geo, const float4 *P, cons
     return uni(cnt);
 }
 
-// stream the neighbours recorded in the masks through the FIFO, each with
-// its r^2 (kept by the first pass, or recomputed past the kept range)
+// stream the neighbours recorded in the masks through the FIFO
 template <class F>
-__device__ __forceinline__ void stream_masks(const float4 *P, const int32_t *cand, const Member &M,
-                                             const MemLds &S, bool wrap, Fifo &q, F &consume)
+__device__ __forceinline__ void stream_masks(const int32_t *cand, int64_t c0, int nc,
+                                             const uint64_t *masks, Fifo &q, F &consume)
 {
-    const float xf = (float)M.xi, yf = (float)M.yi, zf = (float)M.zi, Lf = (float)M.bx.L;
     const int lane = lane_id();
-    const int nch = (M.s.nc + 63) >> 6;
-    const int32_t *cg = cand + M.s.c0;
-    for (int c0 = 0; c0 < nch; c0 += UNR) {
+    const int nch = (nc + 63) >> 6;
+    const int32_t *cg = cand + c0;
+    for (int cb = 0; cb < nch; cb += UNR) {
         uint64_t mk[UNR];
         int j[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; u++) {
-            mk[u] = c0 + u < nch ? readlane_u64(S.masks[c0 + u], 0) : 0ull;
-            j[u] = cg[min(((c0 + u) << 6) + lane, M.s.nc - 1)];
+            mk[u] = cb + u < nch ? readlane_u64(masks[cb + u], 0) : 0ull;
+            j[u] = mk[u] ? cg[min(((cb + u) << 6) + lane, nc - 1)] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < UNR; u++) {
-            const int slot = ((c0 + u) << 6) + lane;
-            float r2f = 0.0f;
-            if ((c0 + u) * 64 < S.rc) {
-                r2f = S.r2c[min(slot, S.rc - 1)];
-            } else if (mk[u]) {
-                const float4 pj = P[j[u]];
-                r2f = r2_f32(pj.x, pj.y, pj.z, xf, yf, zf, Lf, wrap);
-            }
-            q.push((mk[u] >> lane) & 1ull, DEnt{j[u], r2f}, consume);
-        }
+        for (int u = 0; u < UNR; u++) q.push((mk[u] >> lane) & 1ull, DEnt{j[u]}, consume);
     }
     q.flush(consume);
 }
@@ -1163,26 +1233,191 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
     }
     __device__ void take(int j, bool valid, const Pos &p)
     {
-        bool hit = false;
         if constexpr (MODE == 0) {
             const double r2 = r2_of(p.x, p.y, p.z, xi, yi, zi, L, true);
-            hit = valid && r2 < hi * hi;
-            const float r2f = r2_f32((float)p.x, (float)p.y, (float)p.z, (float)xi, (float)yi,
-                                     (float)zi, (float)L, true);
-            q.push(hit, DEnt{j, r2f}, *consume);
+            q.push(valid && r2 < hi * hi, DEnt{j}, *consume);
         } else {
-            const double dx = fold(xi - p.x, L), dy = fold(yi - p.y, L), dz = fold(zi - p.z, L);
-            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double r2 = r2_of(p.x, p.y, p.z, xi, yi, zi, L, true);
             const double hm = fmax(hi, p.h);
-            hit = valid && (j != i) && (r2 < hm * hm);
-            const float Lf = (float)L;
-            q.push(hit,
-                   HEnt{j, fold32((float)xi - (float)p.x, Lf), fold32((float)yi - (float)p.y, Lf),
-                        fold32((float)zi - (float)p.z, Lf)},
-                   *consume);
+            q.push(valid && (j != i) && (r2 < hm * hm), HEnt{j}, *consume);
         }
     }
 };
+
+// ------------------------------------------------------------------ group scan
+// One wave per group: lane m holds member m.  A filter round tests every
+// member still iterating against the group's superset, KB chunks of 64
+// candidates at a time: each lane loads its candidate's FP64 position once
+// per round, and the members' positions come from their lanes (readlane),
+// so the loads and their address arithmetic are shared by the members.  The
+// test is the canonical FP64 one.  In a group that needs no periodic fold
+// the raw differences are the minimum images, so the test is exact as
+// written; in a group that does, every coordinate is moved into the frame of
+// the group's centre (x - s L, s in {-1, 0, 1} per axis) once, and the test
+// decides on those differences outside a band E = 2^-44 (L h + h^2) around
+// h^2 (the two evaluations differ by less than 2^-48 L h + 2^-50 h^2), and on
+// the canonical r^2 of the raw coordinates inside it.  The neighbour mask of
+// each member over each chunk goes to the member's row of a global mask
+// table, which the per-member sum kernels stream.
+constexpr int KB = 4; // candidate chunks held in registers at a time
+
+struct GrpMembers {
+    int a0, M;       // first position in the active list, member count
+    int i;           // lane m: particle
+    double x, y, z;  // lane m: FP64 position (raw)
+    double sx, sy, sz; // lane m: position in the centre's frame (== raw unless the group wraps)
+    double h;        // lane m: smoothing length
+    double d;        // lane m: |x_i - c|
+};
+
+// shift of a coordinate into the frame of the centre c: x - L when it lies
+// more than L/2 above c, x + L when more than L/2 below
+__device__ __forceinline__ double to_frame(double x, double c, double L)
+{
+    const double d = x - c;
+    return d >= 0.5 * L ? x - L : (d < -0.5 * L ? x + L : x);
+}
+
+template <bool HYDRO> struct GrpCand {
+    int j[KB];
+    bool v[KB];
+    double x[KB], y[KB], z[KB];
+    double h[KB]; // hydro: h_j
+};
+
+template <bool WRAP, bool HYDRO>
+__device__ __forceinline__ void load_block(const double4 *__restrict__ p64, const int32_t *cg, int nc,
+                                           int cb, int nch, const GSup &s, double L,
+                                           GrpCand<HYDRO> &c)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int u = 0; u < KB; u++) {
+        const int slot = ((cb + u) << 6) + lane;
+        c.v[u] = slot < nc;
+        c.j[u] = cb + u < nch ? cg[min(slot, nc - 1)] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < KB; u++) {
+        if (cb + u < nch) {
+            const double4 p = p64[c.j[u]];
+            c.x[u] = WRAP ? to_frame(p.x, s.cx, L) : p.x;
+            c.y[u] = WRAP ? to_frame(p.y, s.cy, L) : p.y;
+            c.z[u] = WRAP ? to_frame(p.z, s.cz, L) : p.z;
+            if (HYDRO) c.h[u] = p.w;
+        }
+    }
+}
+
+// One filter round for the members in `ev`: member m's neighbour mask over
+// chunk c goes to rows[m * nchT + c]; lane m returns member m's count.
+// Density: r < h_m.  Hydro: j != i_m and r < max(h_m, h_j).
+template <bool WRAP, bool HYDRO>
+__device__ int group_round(const double4 *__restrict__ p64, const int32_t *cg, const GSup &s,
+                           double L, const GrpMembers &gm, double hm_lane, uint64_t ev,
+                           uint64_t *rows, int nchT, WaveStats &ws)
+{
+    const int lane = lane_id();
+    const int nc = s.nc;
+    const int nch = (nc + 63) >> 6;
+    int cnt = 0;
+    for (int cb = 0; cb < nch; cb += KB) {
+        GrpCand<HYDRO> c;
+        load_block<WRAP, HYDRO>(p64, cg, nc, cb, nch, s, L, c);
+        uint64_t rest = ev;
+        while (rest) {
+            const int m = ctz64(rest);
+            rest &= rest - 1ull;
+            const double xm = uni_d(readlane_d(gm.sx, m)), ym = uni_d(readlane_d(gm.sy, m)),
+                         zm = uni_d(readlane_d(gm.sz, m));
+            const double hmm = uni_d(readlane_d(hm_lane, m));
+            const double h2m = hmm * hmm;
+            const int im = HYDRO ? uni(readlane_i(gm.i, m)) : 0;
+            int sum = 0;
+            uint32_t wlo = 0u, whi = 0u; // lane u: the mask of chunk cb + u
+#pragma unroll
+            for (int u = 0; u < KB; u++) {
+                if (cb + u < nch) {
+                    const double dx = c.x[u] - xm, dy = c.y[u] - ym, dz = c.z[u] - zm;
+                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                    const double hh = HYDRO ? fmax(hmm, c.h[u]) : hmm;
+                    const double lim = HYDRO ? hh * hh : h2m;
+                    bool hit;
+                    if (WRAP) {
+                        const double E = 0x1p-44 * (L * hh + hh * hh);
+                        hit = c.v[u] && r2 < lim - E;
+                        const bool amb = c.v[u] && !hit && r2 <= lim + E;
+                        if (ballot(amb)) {
+                            if (amb) {
+                                // canonical test on the raw coordinates
+                                const double4 p = p64[c.j[u]];
+                                const double rx = uni_d(readlane_d(gm.x, m)),
+                                             ry = uni_d(readlane_d(gm.y, m)),
+                                             rz = uni_d(readlane_d(gm.z, m));
+                                hit = r2_of(p.x, p.y, p.z, rx, ry, rz, L, true) < lim;
+                            }
+                        }
+                    } else {
+                        hit = c.v[u] && r2 < lim;
+                    }
+                    if (HYDRO) hit = hit && c.j[u] != im;
+                    const uint64_t hmask = ballot(hit);
+                    wlo = lane == u ? (uint32_t)hmask : wlo;
+                    whi = lane == u ? (uint32_t)(hmask >> 32) : whi;
+                    sum += popc64(hmask);
+                }
+            }
+            if (lane < KB && cb + lane < nch)
+                rows[(int64_t)m * nchT + cb + lane] = ((uint64_t)whi << 32) | wlo;
+            if (lane == m) cnt += sum;
+        }
+    }
+    ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)nc;
+    return cnt;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// the group's members into the lanes (all of them; `live` marks those that
+// take part: every member, or in a reuse pass those active now)
+__device__ __forceinline__ GrpMembers group_members(const Geom &geo, const GroupArg &ga, int g,
+                                                    const GSup &s, double L, bool wrapf)
+{
+    const int lane = lane_id();
+    GrpMembers gm;
+    gm.a0 = uni(ga.goff[g]);
+    gm.M = min(uni(ga.goff[g + 1]) - gm.a0, 64);
+    gm.i = lane < gm.M ? ga.act[gm.a0 + lane] : 0;
+    gm.x = gm.y = gm.z = gm.h = gm.d = 0.0;
+    if (lane < gm.M) {
+        gm.x = geo.x[gm.i];
+        gm.y = geo.y[gm.i];
+        gm.z = geo.z[gm.i];
+        gm.h = geo.h[gm.i];
+        const double dx = fold(gm.x - s.cx, L), dy = fold(gm.y - s.cy, L), dz = fold(gm.z - s.cz, L);
+        gm.d = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+    }
+    gm.sx = wrapf ? to_frame(gm.x, s.cx, L) : gm.x;
+    gm.sy = wrapf ? to_frame(gm.y, s.cy, L) : gm.y;
+    gm.sz = wrapf ? to_frame(gm.z, s.cz, L) : gm.z;
+    return gm;
+}
+
+// append the members in `dm` (lanes) to the list of members that finish on
+// their own, one atomic per group
+__device__ __forceinline__ void defer_members(uint64_t dm, int a, int32_t *dfr, DevStatus *st)
+{
+    if (!dm) return;
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(&st->n_dfr, (unsigned long long)popc64(dm));
+    const int b = (int)uni_u64(base);
+    if ((dm >> lane_id()) & 1ull) dfr[b + mbcnt(dm)] = a;
+}
 
 } // namespace
 
@@ -1191,25 +1426,31 @@ struct DensK {
     Geom g;
     GroupArg ga;
     CandArg ca;
-    const float4 *pos4; // FP32 x, y, z and m per particle
+    const float4 *pos4;  // FP32 x, y, z and m per particle (walks, own-superset count passes)
+    const double4 *p64;  // FP64 x, y, z, h per particle (group filters, pair terms)
     const float *m;
     float *rho, *fgrad;
     sfc_density_out out;
     DevStatus *st;
     int64_t priv; // offset in the candidate buffer of the private slots (T per wave), -1: none
     const unsigned long long *drift; // reused supersets: [0] largest displacement (FP64 bits), or NULL
-    const int32_t *sel;              // reused supersets: members computed now (drift[3] of them)
-    int n_ngb, dn, max_iter, fixed_h;
+    const uint8_t *active;           // reused supersets: the members computed now
+    int32_t *dfr;                    // members that finish on their own (st->n_dfr of them)
+    double4 *dstate;                 // per active: h, bracket lo, hi and evaluations so far
+    uint64_t *gmask;                 // per active: neighbour masks over its group's chunks
+    uint8_t *gflag;                  // per active: 1 = finished in its group (sums from gmask)
+    int n_ngb, dn, max_iter, fixed_h, nchT;
 };
 
 namespace {
 
 template <int KER, typename ACC> struct DensPair {
-    const double *x, *y, *z;
+    const double4 *p64;
     const float *m;
     double xi, yi, zi, L;
     bool wrap;
-    ACC hinv;
+    double h2;
+    ACC hinv, inv_h2;
     Kahan<ACC> sw, sd;
     struct Term {
         ACC w, d;
@@ -1217,15 +1458,12 @@ template <int KER, typename ACC> struct DensPair {
     __device__ __forceinline__ Term term(const DEnt &e) const
     {
         const int j = e.j;
-        ACC r2;
-        if (sizeof(ACC) == 8) { // FP64 variant: r^2 from the coordinates
-            r2 = (ACC)r2_of(x[j], y[j], z[j], xi, yi, zi, L, wrap);
-        } else {
-            r2 = (ACC)e.r2;
-        }
-        ACC q = sqrt(r2) * hinv;
+        const double4 pj = p64[j];
+        // the canonical FP64 r^2 of the pair, rounded once for the FP32 sums
+        const double r2 = r2_of(pj.x, pj.y, pj.z, xi, yi, zi, L, wrap);
+        const ACC q = sqrt((ACC)r2) * hinv;
         ACC w, dw;
-        kern_eval<KER, ACC>(q, w, dw);
+        kern_eval_u<KER, ACC>(q, tail_u<ACC>(h2, r2, inv_h2, q), w, dw);
         ACC mj = (ACC)m[j];
         Term t;
         t.w = mj * w;
@@ -1240,21 +1478,41 @@ template <int KER, typename ACC> struct DensPair {
 };
 
 template <int KER, typename ACC>
-__device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, const Member &M, double h,
-                                                        bool wrap)
+__device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, double xi, double yi,
+                                                        double zi, double L, double h, bool wrap)
 {
     DensPair<KER, ACC> pp;
-    pp.x = k.g.x;
-    pp.y = k.g.y;
-    pp.z = k.g.z;
+    pp.p64 = k.p64;
     pp.m = k.m;
-    pp.xi = M.xi;
-    pp.yi = M.yi;
-    pp.zi = M.zi;
-    pp.L = M.bx.L;
+    pp.xi = xi;
+    pp.yi = yi;
+    pp.zi = zi;
+    pp.L = L;
     pp.wrap = wrap;
+    pp.h2 = h * h;
     pp.hinv = (ACC)(1.0 / h);
+    pp.inv_h2 = (ACC)(1.0 / (h * h));
     return pp;
+}
+
+// the sums of particle i at its final h: rho, drho/dh, f
+template <int KER, typename ACC>
+__device__ void dens_write_sums(const DensK &k, int i, double h, const DensPair<KER, ACC> &pp)
+{
+    double Sw = (double)wave_sum_f_or_d(pp.sw.value());
+    double Sd = (double)wave_sum_f_or_d(pp.sd.value());
+    if (lane_id() != 0) return;
+    constexpr double C = knorm<KER>();
+    double h3 = h * h * h;
+    double rho = C * Sw / h3;
+    double drho = -C * Sd / (h3 * h);
+    double f = 1.0 / (1.0 + h / (3.0 * rho) * drho);
+    k.rho[i] = (float)rho;
+    k.fgrad[i] = (float)f;
+    if (k.out.drhodh) k.out.drhodh[i] = (float)drho;
+    if (k.out.rho64) k.out.rho64[i] = rho;
+    if (k.out.drhodh64) k.out.drhodh64[i] = drho;
+    if (k.out.fgrad64) k.out.fgrad64[i] = f;
 }
 
 template <int KER, typename ACC>
@@ -1307,7 +1565,7 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
         lo = uni_d(lo);
         hi = uni_d(hi);
     }
-    DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, true);
+    DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M.xi, M.yi, M.zi, M.bx.L, h, true);
     StreamVisit<0, DensPair<KER, ACC>> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi, M.bx.L, h, M.i,
                                           Fifo{(DEnt *)S.fifo, 0}, &pp};
     Ball B{M.xi, M.yi, M.zi, M.bx.L, sq(h * INFL), 0.0, 0.0, 0};
@@ -1317,23 +1575,17 @@ __device__ void dens_solo(const DensK &k, const MemLds &S, const Member &M, doub
     dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
 }
 
-} // namespace
-
-namespace {
-// h iteration on the superset of M: 1 when h is final (in the window, or
-// max_iter evaluations), 0 when h has outgrown the superset (h + d > cov);
+// h iteration on the (own) superset of M: 1 when h is final (in the window,
+// or max_iter evaluations), 0 when h has outgrown the superset (h + d > cov);
 // the masks of the last evaluation stay in LDS
 __device__ __forceinline__ int iterate(const DensK &k, const Member &M, const MemLds &S, double &h,
                                        double &lo, double &hi, int &it, int &nn, bool &conv,
-                                       double dl, WaveStats &ws)
+                                       WaveStats &ws)
 {
-    // a reused superset: every particle may have moved by dl since the walk
-    const double d = (M.s.flags & GSUP_FRESH) ? M.d : M.d + dl;
-    const bool wrap = (M.s.flags & GSUP_WRAP) != 0 || k.drift != nullptr;
     bool first = true;
     while (it < k.max_iter) {
-        if (!(h + d <= M.s.cov)) return 0;
-        nn = count_pass(k.g, k.pos4, k.ca.cand, M, h, wrap, S, first);
+        if (!(h + M.d <= M.s.cov)) return 0;
+        nn = count_pass(k.g, k.pos4, k.ca.cand, M, h, true, S, first);
         ws.tests += (unsigned)M.s.nc;
         first = false;
         it++;
@@ -1376,35 +1628,170 @@ __device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Me
     M.d = 0.0;
     return true;
 }
+
+constexpr int ST_ITER = 0, ST_DONE = 1, ST_DEFER = 2;
+
+// The h loop of one group's members on its superset: every member still
+// iterating is counted in the same round; members that finish write h and
+// their counts and keep their last masks for k_dsum; members whose h
+// outgrows the superset (or whose group kept none) are listed for
+// k_dens_solo with the state they reached.
+template <bool WRAP>
+__device__ void dens_count(const DensK &k, int g, const GSup &s, const BoxInfo &bx, double dl,
+                           WaveStats &ws)
+{
+    const int lane = lane_id();
+    const GrpMembers gm = group_members(k.g, k.ga, g, s, bx.L, WRAP);
+    bool live = lane < gm.M;
+    if (k.active && live) live = k.active[gm.i] != 0; // reuse: the members active now
+    const uint64_t livem = ballot(live);
+    // a reused superset: every particle may have moved by dl since the walk
+    const double d = gm.d + dl;
+    double h = gm.h, lo = 0.0, hi = INFINITY;
+    int it = 0, nn = 0, stt = live ? ST_ITER : ST_DONE;
+    bool conv = false;
+    if (s.flags & GSUP_SOLO) stt = live ? ST_DEFER : stt;
+    const int32_t *cg = k.ca.cand + s.c0;
+    uint64_t *rows = k.gmask + (int64_t)gm.a0 * k.nchT;
+    for (int round = 0; livem && round <= k.max_iter; round++) {
+        const bool over = stt == ST_ITER && !(h + d <= s.cov);
+        if (over) stt = ST_DEFER;
+        const uint64_t ev = ballot(stt == ST_ITER);
+        if (!ev) break;
+        const int cnt = group_round<WRAP, false>(k.p64, cg, s, bx.L, gm, h, ev, rows, k.nchT, ws);
+        if ((ev >> lane) & 1ull) {
+            it++;
+            nn = cnt;
+            if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
+                conv = true;
+                stt = ST_DONE;
+            } else if (it >= k.max_iter) {
+                stt = ST_DONE;
+            } else {
+                h = h_step(nn, k.n_ngb, k.dn, h, lo, hi);
+            }
+        }
+    }
+    const uint64_t dm = ballot(live && stt == ST_DEFER);
+    if ((dm >> lane) & 1ull) k.dstate[gm.a0 + lane] = make_double4(h, lo, hi, (double)it);
+    defer_members(dm, gm.a0 + lane, k.dfr, k.st);
+    ws.deferred += (uint32_t)popc64(dm);
+    const bool done = live && stt == ST_DONE;
+    if (done) {
+        k.g.h[gm.i] = h;
+        if (k.out.nngb) k.out.nngb[gm.i] = nn;
+        if (k.out.iters) k.out.iters[gm.i] = it;
+        if (k.out.converged) k.out.converged[gm.i] = conv ? 1 : 0;
+    }
+    if (lane < gm.M) k.gflag[gm.a0 + lane] = done ? 1 : 0;
+    ws.iters += (uint32_t)uni(wave_sum_i(done ? it : 0));
+    ws.not_conv += (uint32_t)popc64(ballot(done && !conv));
+}
+
+// stream the neighbours of a member's mask row (in global memory) through
+// the FIFO
+template <class F, class Q, class E>
+__device__ __forceinline__ void stream_row(const int32_t *cand, int64_t c0, int nc,
+                                           const uint64_t *row, Q &q, F &consume, int &nn)
+{
+    const int lane = lane_id();
+    const int nch = (nc + 63) >> 6;
+    const int32_t *cg = cand + c0;
+    for (int s0 = 0; s0 < nch; s0 += 64) {
+        const uint64_t rv = s0 + lane < nch ? row[s0 + lane] : 0ull;
+        const int ns = min(64, nch - s0);
+        for (int cb = 0; cb < ns; cb += UNR) {
+            uint64_t mk[UNR];
+            int j[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                mk[u] = cb + u < ns ? readlane_u64(rv, cb + u) : 0ull;
+                j[u] = mk[u] ? cg[min(((s0 + cb + u) << 6) + lane, nc - 1)] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                nn += popc64(mk[u]);
+                q.push((mk[u] >> lane) & 1ull, E{j[u]}, consume);
+            }
+        }
+    }
+    q.flush(consume);
+}
+
 } // namespace
 
-// One wave per active particle: h iteration on the group superset, then the
-// density sums.  A particle whose h outgrows the group superset walks once
-// for a superset of its own, with the bracket's upper end as radius (or 1.25 h
-// while there is none), and iterates on that; only when that fails too does
-// it walk once per h evaluation.
-template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_density(DensK k)
+// One wave per group, groups taken from per-XCD work queues: the group's
+// members iterate h together on its superset; members that outgrow it are
+// listed for k_dens_solo.
+__global__ __launch_bounds__(64) void k_dgroup(DensK k)
+{
+    const int G = uni(*k.ga.n_groups);
+    Queue wq = queue_open(k.st->qctr2, G);
+    WaveStats ws;
+    const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
+    for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
+        const GSup s = load_gsup(k.ca.sup + g);
+        const BoxInfo bx = box_info(k.g, uni(k.ga.act[uni(k.ga.goff[g])]));
+        // a reused superset: positions moved since the walk, pairs may fold
+        if ((s.flags & GSUP_WRAP) || k.drift)
+            dens_count<true>(k, g, s, bx, dl, ws);
+        else
+            dens_count<false>(k, g, s, bx, dl, ws);
+    }
+    ws.flush(k.st);
+}
+
+// One wave per member that finished in its group: the density sums over the
+// neighbours its mask row holds.
+template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_dsum(DensK k)
+{
+    extern __shared__ __align__(16) char lds_raw[];
+    DEnt *fifo = (DEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
+    const int A = uni(*k.ga.n_act);
+    const ItemRange ar = item_range(A);
+    WaveStats ws;
+    for (int a = ar.i; a < ar.end; a += ar.stride) {
+        if (!uni(k.gflag[a])) continue;
+        const int i = uni(k.ga.act[a]);
+        const GSup s = load_gsup(k.ca.sup + uni(k.ca.grp[a]));
+        const BoxInfo bx = box_info(k.g, i);
+        const double h = uni_d(k.g.h[i]);
+        const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
+        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, uni_d(k.g.x[i]), uni_d(k.g.y[i]),
+                                                    uni_d(k.g.z[i]), bx.L, h, wrap);
+        Fifo q{fifo, 0};
+        int nn = 0;
+        stream_row<DensPair<KER, ACC>, Fifo, DEnt>(k.ca.cand, s.c0, s.nc, k.gmask + (int64_t)a * k.nchT,
+                                                   q, pp, nn);
+        ws.pairs += (unsigned)nn;
+        dens_write_sums<KER, ACC>(k, i, h, pp);
+    }
+    ws.flush(k.st);
+}
+
+// One wave per member that left its group superset: a superset of its own
+// (radius: the bracket's upper end, or 1.25 h while there is none), walked
+// up to three times, and the h loop continued on it from where the group
+// left it; only when that fails too does it walk once per h evaluation.
+template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_dens_solo(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const MemLds S = mem_carve(lds_raw, k.ga.T, true);
-    // reuse: the members active now (a list of positions in the active list)
-    const int A = k.sel ? uni((int)k.drift[3]) : uni(*k.ga.n_act);
-    const ItemRange ar = item_range(A);
+    const int D = uni((int)k.st->n_dfr);
+    const ItemRange ar = item_range(D);
     WaveStats ws;
-    const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
     for (int item = ar.i; item < ar.end; item += ar.stride) {
-        const int a = k.sel ? uni(k.sel[item]) : item;
+        const int a = uni(k.dfr[item]);
         Member M = member(k.g, k.ga, k.ca, a);
-        double h = M.h, lo = 0.0, hi = INFINITY;
-        int it = 0, nn = 0;
-        bool conv = false, done = false;
-        bool usable = (M.s.flags & GSUP_SOLO) == 0;
+        const double4 ds = k.dstate[a];
+        double h = uni_d(ds.x), lo = uni_d(ds.y), hi = uni_d(ds.z);
+        int it = uni((int)ds.w), nn = 0;
+        bool conv = false, done = false, usable = false;
         for (int round = 0; round < 4; round++) {
-            if (usable && iterate(k, M, S, h, lo, hi, it, nn, conv, dl, ws)) {
+            if (usable && iterate(k, M, S, h, lo, hi, it, nn, conv, ws)) {
                 done = true;
                 break;
             }
-            if (round == 0) ws.deferred++;
             if (round == 3) break;
             const double rad = hi < INFINITY ? hi : 1.25 * h;
             usable = own_superset(k, S, M, rad, ws);
@@ -1414,10 +1801,9 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_densit
             dens_solo<KER, ACC>(k, S, M, h, lo, hi, it, ws);
             continue;
         }
-        const bool wrap = (M.s.flags & GSUP_WRAP) != 0 || k.drift != nullptr;
-        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M, h, wrap);
+        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, M.xi, M.yi, M.zi, M.bx.L, h, true);
         Fifo q{(DEnt *)S.fifo, 0};
-        stream_masks(k.pos4, k.ca.cand, M, S, wrap, q, pp);
+        stream_masks(k.ca.cand, M.s.c0, M.s.nc, S.masks, q, pp);
         dens_write<KER, ACC>(k, M.i, h, nn, it, conv, pp, ws);
     }
     ws.flush(k.st);
@@ -1431,13 +1817,17 @@ struct HydroK {
     const float *m, *vx, *vy, *vz, *u, *rho, *fgrad;
     const float4 *pa;   // per particle: m, vx, vy, vz
     const float4 *pb;   // per particle: rho, f P / rho^2, sound speed, h
-    const float4 *pos4; // per particle: FP32 x, y, z, h
+    const float4 *pos4; // per particle: FP32 x, y, z, h (walks)
+    const double4 *p64; // per particle: FP64 x, y, z, h (group filters, pair terms)
     const unsigned long long *drift; // reused supersets: largest displacement, h growth, or NULL
-    const int32_t *sel;              // reused supersets: members computed now (drift[3] of them)
+    const uint8_t *active;           // reused supersets: the members computed now
     int32_t *dfr;                    // members that walk alone (st->n_dfr of them)
+    uint64_t *gmask;                 // per active: neighbour masks over its group's chunks
+    uint8_t *gflag;                  // per active: 1 = filtered in its group (sums from gmask)
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
+    int nchT;
 };
 
 namespace {
@@ -1445,6 +1835,7 @@ template <int KER, typename ACC> struct HydroPair {
     const HydroK *k;
     double xi, yi, zi, L;
     bool wrap;
+    double h2;
     ACC hinv, hinv4, vx, vy, vz, rho, pf, cs;
     Kahan<ACC> ax, ay, az, du;
     ACC vmax;
@@ -1455,22 +1846,16 @@ template <int KER, typename ACC> struct HydroPair {
     {
         constexpr ACC C = (ACC)knorm<KER>();
         const int j = e.j;
-        ACC dx, dy, dz;
-        if (sizeof(ACC) == 8) { // FP64 variant: displacement from the coordinates
-            double dxd = xi - k->g.x[j], dyd = yi - k->g.y[j], dzd = zi - k->g.z[j];
-            if (wrap) {
-                dxd = fold(dxd, L);
-                dyd = fold(dyd, L);
-                dzd = fold(dzd, L);
-            }
-            dx = (ACC)dxd;
-            dy = (ACC)dyd;
-            dz = (ACC)dzd;
-        } else {
-            dx = (ACC)e.dx;
-            dy = (ACC)e.dy;
-            dz = (ACC)e.dz;
+        // x_i - x_j (the force direction) in FP64, rounded once for FP32
+        const double4 pj = k->p64[j];
+        double dxd = xi - pj.x, dyd = yi - pj.y, dzd = zi - pj.z;
+        if (wrap) {
+            dxd = fold(dxd, L);
+            dyd = fold(dyd, L);
+            dzd = fold(dzd, L);
         }
+        const ACC dx = (ACC)dxd, dy = (ACC)dyd, dz = (ACC)dzd;
+        const double r2d = __builtin_fma(dzd, dzd, __builtin_fma(dyd, dyd, dxd * dxd));
         ACC mj, vxj, vyj, vzj, rhoj, pfj, csj, hj;
         if (sizeof(ACC) == 8) {
             double gm1 = k->gamma - 1.0;
@@ -1478,7 +1863,7 @@ template <int KER, typename ACC> struct HydroPair {
             rhoj = (ACC)k->rho[j];
             pfj = (ACC)(k->fgrad[j] * gm1 * uj / (double)k->rho[j]);
             csj = (ACC)sqrt(k->gamma * gm1 * uj);
-            hj = (ACC)k->g.h[j];
+            hj = (ACC)pj.w;
             mj = (ACC)k->m[j];
             vxj = (ACC)k->vx[j];
             vyj = (ACC)k->vy[j];
@@ -1495,13 +1880,14 @@ template <int KER, typename ACC> struct HydroPair {
             csj = (ACC)b.z;
             hj = (ACC)b.w;
         }
-        ACC r2 = mad(dz, dz, mad(dy, dy, dx * dx));
-        ACC r = sqrt(r2);
+        ACC r = sqrt((ACC)r2d);
         ACC rinv = r > ACC(0) ? ACC(1) / r : ACC(0);
         ACC w, dwi, dwj;
-        kern_eval<KER, ACC>(r * hinv, w, dwi);
+        const ACC qi = r * hinv;
+        kern_eval_u<KER, ACC>(qi, tail_u<ACC>(h2, r2d, hinv * hinv, qi), w, dwi);
         ACC hjinv = ACC(1) / hj;
-        kern_eval<KER, ACC>(r * hjinv, w, dwj);
+        const ACC qj = r * hjinv;
+        kern_eval_u<KER, ACC>(qj, tail_u<ACC>(pj.w * pj.w, r2d, hjinv * hjinv, qj), w, dwj);
         ACC hj2 = hjinv * hjinv;
         ACC dWi = C * dwi * hinv4;
         ACC dWj = C * dwj * (hj2 * hj2);
@@ -1532,17 +1918,18 @@ template <int KER, typename ACC> struct HydroPair {
 };
 
 template <int KER, typename ACC>
-__device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, const Member &M, bool wrap)
+__device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, int i, double xi, double yi,
+                                                          double zi, double L, double h, bool wrap)
 {
-    const int i = M.i;
     HydroPair<KER, ACC> hp;
     hp.k = &k;
-    hp.xi = M.xi;
-    hp.yi = M.yi;
-    hp.zi = M.zi;
-    hp.L = M.bx.L;
+    hp.xi = xi;
+    hp.yi = yi;
+    hp.zi = zi;
+    hp.L = L;
     hp.wrap = wrap;
-    double hinv = 1.0 / M.h;
+    double hinv = 1.0 / h;
+    hp.h2 = h * h;
     hp.hinv = (ACC)hinv;
     hp.hinv4 = (ACC)(hinv * hinv * hinv * hinv);
     hp.vx = (ACC)k.vx[i];
@@ -1581,16 +1968,46 @@ __device__ void hydro_write(const HydroK &k, int i, const HydroPair<KER, ACC> &h
     if (k.out.az64) k.out.az64[i] = az;
     if (k.out.dudt64) k.out.dudt64[i] = du;
 }
+
+// The hydro filter of one group: one round for the members its superset
+// covers; their masks go to their rows for k_hsum, the others are listed
+// for k_hydro_solo.
+template <bool WRAP>
+__device__ void hydro_filter(const HydroK &k, int g, const GSup &s, const BoxInfo &bx, double dl,
+                             double dh, WaveStats &ws)
+{
+    const int lane = lane_id();
+    const GrpMembers gm = group_members(k.g, k.ga, g, s, bx.L, WRAP);
+    bool live = lane < gm.M;
+    if (k.active && live) live = k.active[gm.i] != 0; // reuse: the members active now
+    const uint64_t livem = ballot(live);
+    // a reused superset still covers a member while its sphere, grown by
+    // the drift, stays inside the walked ball (and its radius for h_j)
+    const bool kept = !k.drift || (gm.h + gm.d + dl <= s.cov && gm.d + dl + dh <= s.rs);
+    const uint64_t dm = (s.flags & GSUP_SOLO) ? livem : ballot(live && !kept);
+    defer_members(dm, gm.a0 + lane, k.dfr, k.st);
+    ws.deferred += (uint32_t)popc64(dm);
+    const uint64_t ev = livem & ~dm;
+    if (lane < gm.M) k.gflag[gm.a0 + lane] = (ev >> lane) & 1ull ? 1 : 0;
+    if (!ev) return;
+    const int32_t *cg = k.ca.cand + s.c0;
+    uint64_t *rows = k.gmask + (int64_t)gm.a0 * k.nchT;
+    const int cnt = group_round<WRAP, true>(k.p64, cg, s, bx.L, gm, gm.h, ev, rows, k.nchT, ws);
+    ws.pairs += (unsigned long long)uni(wave_sum_i(cnt));
+}
 } // namespace
 
 __global__ void k_dens_prep(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                            const double *__restrict__ z, const float *__restrict__ m,
-                            float4 *__restrict__ pos4, double4 *__restrict__ snap)
+                            const double *__restrict__ z, const double *__restrict__ h,
+                            const float *__restrict__ m, float4 *__restrict__ pos4,
+                            double4 *__restrict__ p64, double4 *__restrict__ snap)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], m[i]);
-    if (snap) snap[i] = make_double4(x[i], y[i], z[i], 0.0);
+    const double xi = x[i], yi = y[i], zi = z[i];
+    pos4[i] = make_float4((float)xi, (float)yi, (float)zi, m[i]);
+    p64[i] = make_double4(xi, yi, zi, h[i]);
+    if (snap) snap[i] = make_double4(xi, yi, zi, 0.0);
 }
 
 // Drift since the snapshot of kept supersets: the largest displacement
@@ -1676,124 +2093,71 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
                              const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ z, double gamma, float4 *__restrict__ pa,
                              float4 *__restrict__ pb, float4 *__restrict__ pos4,
-                             double4 *__restrict__ snap)
+                             double4 *__restrict__ p64, double4 *__restrict__ snap)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (snap) snap[i] = make_double4(x[i], y[i], z[i], h[i]);
+    const double xi = x[i], yi = y[i], zi = z[i], hi = h[i];
+    if (snap) snap[i] = make_double4(xi, yi, zi, hi);
     double gm1 = gamma - 1.0;
     double uu = u[i];
     pa[i] = make_float4(m[i], vx[i], vy[i], vz[i]);
-    pos4[i] = make_float4((float)x[i], (float)y[i], (float)z[i], (float)h[i]);
+    pos4[i] = make_float4((float)xi, (float)yi, (float)zi, (float)hi);
+    p64[i] = make_double4(xi, yi, zi, hi);
     pb[i] = make_float4(rho[i], (float)(fgrad[i] * gm1 * uu / (double)rho[i]),
-                        (float)sqrt(gamma * gm1 * uu), (float)h[i]);
+                        (float)sqrt(gamma * gm1 * uu), (float)hi);
 }
 
-// One wave per active particle: filter the group superset with
-// r < max(h_i, h_j), j != i, and sum the forces.
-// FP32 sums: five waves per SIMD (the register cut, a few spills, pays for
-// itself in latency hiding)
-template <int KER, typename ACC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? 5 : 1))) void k_hydro(HydroK k)
+// One wave per group (groups from per-XCD work queues): one filter round of
+// its members over the superset with r < max(h_i, h_j), j != i.  Members
+// that the superset does not cover are listed for k_hydro_solo.
+__global__ __launch_bounds__(64) void k_hgroup(HydroK k)
 {
-    extern __shared__ __align__(16) char lds_raw[];
-    const MemLds S = mem_carve(lds_raw, k.ga.T, false);
-    const int lane = lane_id();
-    const int A = k.sel ? uni((int)k.drift[3]) : uni(*k.ga.n_act);
-    const ItemRange ar = item_range(A);
+    const int G = uni(*k.ga.n_groups);
+    Queue wq = queue_open(k.st->qctr2, G);
     WaveStats ws;
     // reused supersets: the largest displacement and h growth since the walk
     const double dl = k.drift ? __longlong_as_double((long long)k.drift[0]) : 0.0;
     const double dh = k.drift ? __longlong_as_double((long long)k.drift[1]) : 0.0;
-    for (int item = ar.i; item < ar.end; item += ar.stride) {
-        const int a = k.sel ? uni(k.sel[item]) : item;
-        const Member M = member(k.g, k.ga, k.ca, a);
-        const bool kept = !k.drift || (M.h + M.d + dl <= M.s.cov && M.d + dl + dh <= M.s.rs);
-        if ((M.s.flags & GSUP_SOLO) || !kept) {
-            ws.deferred++;
-            if (k.drift) { // reuse (many members may walk alone): in k_hydro_solo
-                if (lane == 0) k.dfr[atomicAdd(&k.st->n_dfr, 1ull)] = a;
-                continue;
-            }
-            HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
-            StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
-                                                   M.bx.L, M.h, M.i, FifoH{(HEnt *)S.fifo, 0}, &hp};
-            Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
-            walk(k.g, M.bx.root, M.bx.root_end, B, sv, k.st);
-            ws.walks++;
-            sv.q.flush(hp);
-            hydro_write<KER, ACC>(k, M.i, hp);
-            continue;
-        }
-        const bool wrap = (M.s.flags & GSUP_WRAP) != 0 || k.drift != nullptr;
-        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, wrap);
-        FifoH q{(HEnt *)S.fifo, 0};
-        // the filter decides r < max(h_i, h_j) on FP32 positions and h (as
-        // the density count pass does, band widened for the FP32 h and the
-        // FP32 band arithmetic), and in FP64 inside the band
-        const float xf = (float)M.xi, yf = (float)M.yi, zf = (float)M.zi, Lf = (float)M.bx.L,
-                    hf = (float)M.h;
-        const int nc = M.s.nc;
-        const int nch = (nc + 63) >> 6;
-        const int32_t *cg = k.ca.cand + M.s.c0;
-        ws.tests += (unsigned)nc;
-        int jn[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; u++) jn[u] = cg[min((u << 6) + lane, nc - 1)];
-        for (int c0 = 0; c0 < nch; c0 += UNR) {
-            int j[UNR];
-            bool v[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                v[u] = ((c0 + u) << 6) + lane < nc;
-                j[u] = jn[u];
-            }
-            float4 pj[UNR]; // x, y, z, h
-#pragma unroll
-            for (int u = 0; u < UNR; u++) pj[u] = k.pos4[j[u]];
-#pragma unroll
-            for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                // x_i - x_j (the force direction) of the FP32 positions, folded
-                // when pairs need it
-                float dx = xf - pj[u].x, dy = yf - pj[u].y, dz = zf - pj[u].z;
-                if (wrap) {
-                    dx = fold32(dx, Lf);
-                    dy = fold32(dy, Lf);
-                    dz = fold32(dz, Lf);
-                }
-                const float r2f = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                const float hmf = fmaxf(hf, pj[u].w);
-                const float hm2f = hmf * hmf;
-                const float E = 0x1p-19f * __builtin_fmaf(Lf, hmf, hm2f);
-                bool hit = r2f < hm2f - E;
-                const bool amb = v[u] && !hit && !(r2f > hm2f + E);
-                if (ballot(amb)) { // inside the band: the FP64 test decides
-                    if (amb) {
-                        const int jj = j[u];
-                        const double hm = fmax(M.h, k.g.h[jj]);
-                        hit = r2_of(k.g.x[jj], k.g.y[jj], k.g.z[jj], M.xi, M.yi, M.zi, M.bx.L,
-                                    wrap) < hm * hm;
-                    }
-                }
-                const bool pair = v[u] && j[u] != M.i && hit;
-                ws.pairs += (unsigned)popc64(ballot(pair));
-                q.push(pair, HEnt{j[u], dx, dy, dz}, hp);
-            }
-        }
-        q.flush(hp);
-        hydro_write<KER, ACC>(k, M.i, hp);
+    for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
+        const GSup s = load_gsup(k.ca.sup + g);
+        const BoxInfo bx = box_info(k.g, uni(k.ga.act[uni(k.ga.goff[g])]));
+        if ((s.flags & GSUP_WRAP) || k.drift)
+            hydro_filter<true>(k, g, s, bx, dl, dh, ws);
+        else
+            hydro_filter<false>(k, g, s, bx, dl, dh, ws);
     }
     ws.flush(k.st);
 }
 
-// The hydro members that a reuse call of k_hydro deferred (their group kept
-// no superset, or the reused one no longer covers them): one wave each walks
-// the tree level by level and streams its pairs into the sums.  A kernel of
-// their own keeps that walk out of k_hydro's register budget; the few
-// members of an ordinary call walk inside k_hydro (window walk), where their
-// walks overlap the other waves' work.
+// One wave per member filtered in its group: the force sums over the
+// neighbours its mask row holds.
+template <int KER, typename ACC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? 5 : 1))) void k_hsum(HydroK k)
+{
+    extern __shared__ __align__(16) char lds_raw[];
+    HEnt *fifo = (HEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
+    const int A = uni(*k.ga.n_act);
+    const ItemRange ar = item_range(A);
+    for (int a = ar.i; a < ar.end; a += ar.stride) {
+        if (!uni(k.gflag[a])) continue;
+        const int i = uni(k.ga.act[a]);
+        const GSup s = load_gsup(k.ca.sup + uni(k.ca.grp[a]));
+        const BoxInfo bx = box_info(k.g, i);
+        const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
+        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, i, uni_d(k.g.x[i]), uni_d(k.g.y[i]),
+                                                      uni_d(k.g.z[i]), bx.L, uni_d(k.g.h[i]), wrap);
+        FifoH q{fifo, 0};
+        int nn = 0;
+        stream_row<HydroPair<KER, ACC>, FifoH, HEnt>(k.ca.cand, s.c0, s.nc,
+                                                     k.gmask + (int64_t)a * k.nchT, q, hp, nn);
+        hydro_write<KER, ACC>(k, i, hp);
+    }
+}
+
+// The hydro members that their group's superset does not cover (their group
+// kept none, or a reused one no longer covers them): one wave each walks the
+// tree level by level and streams its pairs into the sums.
 constexpr int HSOLO_WAVE_LDS = FIFO_BYTES + 4 * (2 * LCAP + 64);
 template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro_solo(HydroK k)
 {
@@ -1809,7 +2173,7 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro_
     WaveStats ws;
     for (int item = ar.i; item < ar.end; item += ar.stride) {
         const Member M = member(k.g, k.ga, k.ca, uni(k.dfr[item]));
-        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M, true);
+        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M.i, M.xi, M.yi, M.zi, M.bx.L, M.h, true);
         StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
                                                M.bx.L, M.h, M.i, FifoH{(HEnt *)S.fifo, 0}, &hp};
         Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
@@ -1995,6 +2359,12 @@ CandArg make_cand(const SearchBufs &sb)
     return c;
 }
 
+template <class Kern> hipError_t allow_lds(Kern kern, size_t lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 // persistent grid: as many workgroups as fit on the chip at once (a multiple
 // of 8), so that every wave is resident and keeps its XCD's items
 template <class Kern>
@@ -2016,16 +2386,13 @@ template <class Kern, class Arg>
 hipError_t launch_persistent(Kern kern, hipStream_t s, const Arg &a, int threads, size_t lds, int cu,
                              int64_t max_items)
 {
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = allow_lds(kern, lds);
+    if (e != hipSuccess) return e;
     kern<<<grid_size(kern, threads, lds, cu, max_items), threads, lds, s>>>(a);
     return hipGetLastError();
 }
 
-constexpr int MEM_WAVES = 4; // member waves per workgroup
+constexpr int MEM_WAVES = 4; // member waves per workgroup of the solo kernels
 
 hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
                        SearchBufs &sb, DevStatus *st, int T, double skin, int hydro)
@@ -2064,49 +2431,49 @@ hipError_t launch_drift(hipStream_t s, const PartDev &p, const double *h, const 
                                                                    sb.drift + 3);
     return hipGetLastError();
 }
-} // namespace
 
-namespace {
-// The density pass: the walk of the groups, then k_density on a persistent
-// grid.  Each wave of that grid owns a private slot of T candidates at the end
-// of the buffer (when the slots take at most half of it); the group supersets
-// use the rest.
+// The density pass: the walk of the groups, k_dgroup (the h loop of every
+// group's members on its superset), k_dens_solo (the members that left their
+// group superset) and k_dsum (the sums of the others).  Each wave of
+// k_dens_solo owns a private slot of T candidates at the end of the
+// candidate buffer (when the slots take at most half of it); the group
+// supersets use the rest.
 template <int KER, typename ACC>
 hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
                        const SearchBufs &sb, const DensityArgs &a, DevStatus *st)
 {
     const sfc_density_params &dp = a.dp;
-    const size_t lds = MEM_WAVES * mem_lds_bytes(dp.t_cand, true);
-    const int th = 64 * MEM_WAVES;
-    auto kern = k_density<KER, ACC>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    const unsigned grid = grid_size(kern, th, lds, sb.cu_count, p.n);
-    const int64_t priv = (int64_t)grid * MEM_WAVES * dp.t_cand;
+    const int T = dp.t_cand;
+    auto ks = k_dens_solo<KER, ACC>;
+    auto kb = k_dsum<KER, ACC>;
+    const size_t lds_s = MEM_WAVES * mem_lds_bytes(T, true);
+    const size_t lds_b = (size_t)MEM_WAVES * FIFO_BYTES;
+    hipError_t e = allow_lds(ks, lds_s);
+    if (e != hipSuccess) return e;
+    // the members that leave their group are few: one workgroup per CU
+    const unsigned grid_s = (unsigned)((sb.cu_count + 7) / 8 * 8);
+    const int64_t priv = (int64_t)grid_s * MEM_WAVES * T;
     SearchBufs gs = sb;
     if (priv <= sb.cand_cap / 2) gs.cand_cap = sb.cand_cap - priv;
-    k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.m, sb.pos4,
-                                                              a.keep ? sb.snap : nullptr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.h, p.m, sb.pos4,
+                                                              sb.p64, a.keep ? sb.snap : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (dp.reuse) {
         // the kept supersets: the walk is skipped, the drift bounds them
         k_reset_pass<<<1, 64, 0, s>>>(st);
         e = launch_drift(s, p, nullptr, g, sb);
     } else {
-        e = launch_walk(s, p, t, g, gs, st, dp.t_cand, dp.skin, 0);
+        e = launch_walk(s, p, t, g, gs, st, T, dp.skin, 0);
     }
     if (e != hipSuccess) return e;
     DensK k;
     memset(&k, 0, sizeof(k));
     k.g = make_geom(p, t);
-    k.ga = make_groups(g, dp.t_cand);
+    k.ga = make_groups(g, T);
     k.ca = make_cand(gs);
     k.priv = gs.cand_cap < sb.cand_cap ? gs.cand_cap : -1;
     k.pos4 = sb.pos4;
+    k.p64 = sb.p64;
     k.m = p.m;
     k.rho = p.rho;
     k.fgrad = p.fgrad;
@@ -2116,13 +2483,34 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.dn = dp.dn;
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
+    k.nchT = T / 64;
     k.drift = dp.reuse ? sb.drift : nullptr;
-    k.sel = dp.reuse ? sb.sel : nullptr;
-    kern<<<grid, th, lds, s>>>(k);
-    e = hipGetLastError();
-    if (e != hipSuccess || !dp.reuse) return e;
+    k.active = dp.reuse ? p.active : nullptr;
+    k.dfr = sb.dfr;
+    k.dstate = sb.dstate;
+    k.gmask = sb.gmask;
+    k.gflag = sb.gflag;
+    if ((e = launch_persistent(k_dgroup, s, k, 64, 0, sb.cu_count, p.n)) != hipSuccess) return e;
+    ks<<<grid_s, 64 * MEM_WAVES, lds_s, s>>>(k);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_persistent(kb, s, k, 64 * MEM_WAVES, lds_b, sb.cu_count, p.n)) != hipSuccess)
+        return e;
+    if (!dp.reuse) return hipSuccess;
     k_reuse_check<<<1, 64, 0, s>>>(sb.drift, st);
     return hipGetLastError();
+}
+
+template <int KER, typename ACC>
+hipError_t run_hydro(hipStream_t s, const HydroK &k, const SearchBufs &sb, int64_t n)
+{
+    const size_t lds_s = (size_t)MEM_WAVES * HSOLO_WAVE_LDS;
+    const size_t lds_b = (size_t)MEM_WAVES * FIFO_BYTES;
+    hipError_t e = launch_persistent(k_hgroup, s, k, 64, 0, sb.cu_count, n);
+    if (e == hipSuccess)
+        e = launch_persistent(k_hydro_solo<KER, ACC>, s, k, 64 * MEM_WAVES, lds_s, sb.cu_count, n);
+    if (e == hipSuccess)
+        e = launch_persistent(k_hsum<KER, ACC>, s, k, 64 * MEM_WAVES, lds_b, sb.cu_count, n);
+    return e;
 }
 } // namespace
 
@@ -2143,7 +2531,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k_hydro_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.m, p.vx, p.vy, p.vz, p.rho,
                                                                p.fgrad, p.u, p.h, p.x, p.y, p.z,
                                                                hp.gamma, sb.pa, sb.pb, sb.pos4,
-                                                               a.keep ? sb.snap : nullptr);
+                                                               sb.p64, a.keep ? sb.snap : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (hp.reuse) {
@@ -2168,34 +2556,22 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.pa = sb.pa;
     k.pb = sb.pb;
     k.pos4 = sb.pos4;
+    k.p64 = sb.p64;
     k.out = a.out;
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
+    k.nchT = hp.t_cand / 64;
+    k.gmask = sb.gmask;
+    k.gflag = sb.gflag;
     k.drift = hp.reuse ? sb.drift : nullptr;
-    k.sel = hp.reuse ? sb.sel : nullptr;
+    k.active = hp.reuse ? p.active : nullptr;
     k.dfr = sb.dfr;
-    const size_t lds = MEM_WAVES * mem_lds_bytes(hp.t_cand, false);
-    const size_t lds_s = (size_t)MEM_WAVES * HSOLO_WAVE_LDS;
-    const int th = 64 * MEM_WAVES;
     const int64_t n = p.n;
-    if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32) {
-        e = launch_persistent(k_hydro<0, float>, s, k, th, lds, sb.cu_count, n);
-        if (e == hipSuccess && hp.reuse)
-            e = launch_persistent(k_hydro_solo<0, float>, s, k, th, lds_s, sb.cu_count, n);
-    } else if (hp.kernel == 0) {
-        e = launch_persistent(k_hydro<0, double>, s, k, th, lds, sb.cu_count, n);
-        if (e == hipSuccess && hp.reuse)
-            e = launch_persistent(k_hydro_solo<0, double>, s, k, th, lds_s, sb.cu_count, n);
-    } else if (hp.accum == SFC_ACCUM_F32) {
-        e = launch_persistent(k_hydro<1, float>, s, k, th, lds, sb.cu_count, n);
-        if (e == hipSuccess && hp.reuse)
-            e = launch_persistent(k_hydro_solo<1, float>, s, k, th, lds_s, sb.cu_count, n);
-    } else {
-        e = launch_persistent(k_hydro<1, double>, s, k, th, lds, sb.cu_count, n);
-        if (e == hipSuccess && hp.reuse)
-            e = launch_persistent(k_hydro_solo<1, double>, s, k, th, lds_s, sb.cu_count, n);
-    }
+    if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32) e = run_hydro<0, float>(s, k, sb, n);
+    else if (hp.kernel == 0) e = run_hydro<0, double>(s, k, sb, n);
+    else if (hp.accum == SFC_ACCUM_F32) e = run_hydro<1, float>(s, k, sb, n);
+    else e = run_hydro<1, double>(s, k, sb, n);
     if (e != hipSuccess || !hp.reuse) return e;
     k_reuse_check<<<1, 64, 0, s>>>(sb.drift, st);
     return hipGetLastError();

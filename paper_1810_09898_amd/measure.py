@@ -267,6 +267,40 @@ def _bin_configs():
     return {0: c, 1: c, 2: c}
 
 
+def ngroup_sweep(w, steps, caps=(1, 8, 16, 32, 64)):
+    """The density pass on the 262 144-particle clustered workload (N_ngb =
+    64, 10 % active) for group caps N_group in `caps`, count policy and the
+    paper's policy with f = 0.5 (the analogue of the paper's hand sweep of f,
+    section "Results"): per case the density call's device time, the whole
+    step's, mean group size, candidates per active and tests per active."""
+    import torch
+    from . import sfcngb as S
+    from .pipeline import Pipeline, StepConfig
+    A = int(w.state["active"].sum())
+    base = None
+    for pol, name in ((S.POLICY_COUNT, "count"), (S.POLICY_PAPER, "paper f=0.5")):
+        for cap in caps:
+            cfg = StepConfig(n_leaf=16, policy=pol, n_group_max=cap, f=0.5, t_cand=1024,
+                             hydro_t_cand=1024)
+            pl = Pipeline(w, cfg)
+            pl.step()
+            torch.cuda.synchronize()
+            pl.ctx.status_clear()
+            pl.step()
+            st = pl.ctx.status(raise_on_overflow=False)
+            ph = _phases(pl, steps)
+            if base is None:
+                base = ph["density"]
+            line = {"sweep": "N_group", "workload": w.name, "policy": name, "n_group_max": cap,
+                    "density_ms": round(ph["density"], 4), "step_ms": round(sum(ph.values()), 4),
+                    "speedup_vs_ungrouped": round(base / ph["density"], 3),
+                    "groups": st["n_groups"], "mean_group_size": round(A / max(st["n_groups"], 1), 2),
+                    "cand_per_active": round(st["sum_cand"] / A, 1),
+                    "tests_per_active": round(st["sum_tests"] / A, 1), "flags": st["flags"]}
+            print(json.dumps(line), flush=True)
+            del pl
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="lognormal_hydro")
@@ -275,6 +309,8 @@ def main():
     ap.add_argument("--fracs", default="0.05,0.1,0.3")
     ap.add_argument("--reuse-bins", type=float, default=0.0,
                     help="skin: finer bins of lognormal_bins on the full step's supersets")
+    ap.add_argument("--sweep", action="store_true",
+                    help="plummer_clustered: the N_group sweep {1, 8, 16, 32, 64}")
     args = ap.parse_args()
     from . import workloads as W
     from . import autotune
@@ -286,7 +322,9 @@ def main():
     w = W.WORKLOADS[args.workload]()
     print(f"# {args.workload}: generated in {time.time() - t0:.1f} s, n={w.n}", file=sys.stderr,
           flush=True)
-    if args.reuse_bins:
+    if args.sweep:
+        ngroup_sweep(w, args.steps)
+    elif args.reuse_bins:
         reuse_bins(w, args.steps, args.reuse_bins, float(args.fracs.split(",")[0]))
     elif args.reuse:
         cfg = StepConfig(n_leaf=128, n_group_max=24, f=0.5, t_cand=2048, hydro_t_cand=2048)

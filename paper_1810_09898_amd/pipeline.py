@@ -24,7 +24,6 @@ class StepConfig:
     policy: int = S.POLICY_PAPER
     n_group_max: int = 32
     f: float = 0.5
-    chunk: int = 1024
     level: int = 5  # tree policy: depth of the grouping nodes
     t_cand: int = 2048
     hydro_t_cand: int = 2048
@@ -102,7 +101,7 @@ class Pipeline:
 
     def groups(self, verify=None, t_cand=None):
         c = self.cfg
-        self.ctx.group_ngb_search(self.ps, c.policy, c.n_group_max, c.f, c.chunk,
+        self.ctx.group_ngb_search(self.ps, c.policy, c.n_group_max, c.f,
                                   gp_box=self.gp_box, verify=verify,
                                   t_cand=t_cand or c.t_cand, level=c.level)
 

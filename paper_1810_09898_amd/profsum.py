@@ -8,9 +8,10 @@
         per-call counter totals from `rocprofv3 --pmc ... --output-format csv`
         runs of bench.py, as JSON and as a text table (OUT with .txt).  FETCH_SIZE / WRITE_SIZE (KiB per dispatch) are
         scaled by the reading of a plain copy of known size (calib.py) to give
-        HBM bytes.  A "call" is one library entry point: density = the walk
-        and the per-particle kernel; hydro_force = the max-h refit, the record
-        kernel, the walk and the per-particle kernel.  The source hash of the
+        HBM bytes; TCC_HIT / TCC_MISS give the L2 hit rate.  A "call" is one
+        library entry point: density = the record kernel, the walk, the group
+        kernel, the solo kernel and the sum kernel; hydro_force = the max-h
+        refit, the record kernel, the walk, the group, solo and sum kernels.  The source hash of the
         search kernels is stored so that the numbers are dropped once the
         kernels change.
 """
@@ -71,27 +72,44 @@ def _dispatches(rows):
     return out
 
 
+DENS_CALL = ("k_dens_prep", "k_reset_pass", "k_walk", "k_dgroup", "k_dens_solo")
+HYDRO_CALL = ("k_tree_leaves", "k_tree_up3", "k_tree_nchild", "k_hydro_prep", "k_reset_pass",
+              "k_walk", "k_hgroup", "k_hydro_solo")
+
+
 def _calls(disp):
-    """split the dispatch sequence into density and hydro_force calls"""
+    """split the dispatch sequence into density and hydro_force calls: each
+    call ends with its per-member sum kernel; the kernels before it back to
+    the call's first one belong to it"""
     items = list(disp.items())
     calls = {"density": [], "hydro_force": []}
     for k, (_, (name, _cs)) in enumerate(items):
-        if name == "k_density":
+        for last, before, call in (("k_dsum", DENS_CALL, "density"),
+                                   ("k_hsum", HYDRO_CALL, "hydro_force")):
+            if name != last:
+                continue
             seg = [items[k]]
             j = k - 1
-            while j >= 0 and items[j][1][0] in ("k_walk", "k_reset_pass") and len(seg) < 3:
+            while j >= 0 and items[j][1][0] in before and len(seg) < 16:
                 seg.insert(0, items[j])
                 j -= 1
-            calls["density"].append(seg)
-        if name == "k_hydro":
-            seg = [items[k]]
-            j = k - 1
-            while j >= 0 and items[j][1][0] in ("k_walk", "k_reset_pass", "k_hydro_prep",
-                                                 "k_tree_leaves", "k_tree_up3", "k_tree_nchild"):
-                seg.insert(0, items[j])
-                j -= 1
-            calls["hydro_force"].append(seg)
+            calls[call].append(seg)
     return calls
+
+
+def _derived(m, f_fetch, f_write):
+    """HBM bytes from the copy-calibrated FETCH_SIZE / WRITE_SIZE (KiB), the L2
+    hit rate from TCC_HIT / TCC_MISS"""
+    e = dict(m)
+    if "FETCH_SIZE" in m and "WRITE_SIZE" in m:
+        e["hbm_bytes"] = m["FETCH_SIZE"] * 1024 * f_fetch + m["WRITE_SIZE"] * 1024 * f_write
+    hit = m.get("TCC_HIT_sum", m.get("TCC_HIT"))
+    miss = m.get("TCC_MISS_sum", m.get("TCC_MISS"))
+    if hit is not None and miss is not None and hit + miss > 0:
+        e["l2_hit_rate"] = hit / (hit + miss)
+    if "SQ_INSTS_VALU" in m:
+        e["valu_insts"] = m["SQ_INSTS_VALU"]
+    return e
 
 
 def pmc(out: str, cmd: str, calib_fetch: str, calib_write: str, runs) -> dict:
@@ -119,18 +137,11 @@ def pmc(out: str, cmd: str, calib_fetch: str, calib_write: str, runs) -> dict:
     res = {"src_hash": src_hash(), "command": cmd, "copy_factor_fetch": f_fetch,
            "copy_factor_write": f_write, "calls": {}, "kernels": {}}
     for call, cs in per_call.items():
-        m = {c: sum(v) / len(v) for c, v in cs.items()}
-        e = {k: m[k] for k in sorted(m)}
-        if "FETCH_SIZE" in m and "WRITE_SIZE" in m:
-            e["hbm_bytes"] = m["FETCH_SIZE"] * 1024 * f_fetch + m["WRITE_SIZE"] * 1024 * f_write
-        if "SQ_INSTS_VALU" in m:
-            e["valu_insts"] = m["SQ_INSTS_VALU"]
-        res["calls"][call] = e
+        m = {c: sum(v) / len(v) for c, v in sorted(cs.items())}
+        res["calls"][call] = _derived(m, f_fetch, f_write)
     for k, cs in per_kernel.items():
         m = {c: sum(v) / len(v) for c, v in sorted(cs.items())}
-        if "FETCH_SIZE" in m and "WRITE_SIZE" in m:
-            m["hbm_bytes"] = m["FETCH_SIZE"] * 1024 * f_fetch + m["WRITE_SIZE"] * 1024 * f_write
-        res["kernels"][k] = m
+        res["kernels"][k] = _derived(m, f_fetch, f_write)
     with open(out, "w") as fh:
         json.dump(res, fh, indent=1)
     with open(os.path.splitext(out)[0] + ".txt", "w") as fh:
@@ -139,9 +150,9 @@ def pmc(out: str, cmd: str, calib_fetch: str, calib_write: str, runs) -> dict:
 
 
 def _table(res) -> str:
-    cols = (("hbm_bytes", "HBM GB", 1e9), ("SQ_INSTS_VALU", "VALU M", 1e6),
-            ("SQ_INSTS_SALU", "SALU M", 1e6), ("SQ_INSTS_LDS", "LDS M", 1e6),
-            ("SQ_INSTS_VMEM_RD", "VMEM M", 1e6))
+    cols = (("hbm_bytes", "HBM GB", 1e9), ("l2_hit_rate", "L2 hit", 1.0),
+            ("SQ_INSTS_VALU", "VALU M", 1e6), ("SQ_INSTS_SALU", "SALU M", 1e6),
+            ("SQ_INSTS_LDS", "LDS M", 1e6), ("SQ_INSTS_VMEM_RD", "VMEM M", 1e6))
     lines = ["# PMC counters per call and per kernel, 2M lognormal step (benchmark configuration)",
              f"# {res['command']}",
              f"# copy-kernel calibration: FETCH_SIZE x {res['copy_factor_fetch']:.4f}, "
@@ -154,9 +165,9 @@ def _table(res) -> str:
     for name, v in rows:
         if v.get("hbm_bytes", 0.0) < 1e7 and not name.startswith("call"):
             continue
-        lines.append(f"{name[:30]:30s} " + " ".join(f"{v.get(c, 0.0) / sc:9.3f}" if c == "hbm_bytes"
-                                                  else f"{v.get(c, 0.0) / sc:9.1f}"
-                                                  for c, _, sc in cols))
+        lines.append(f"{name[:30]:30s} " + " ".join(
+            f"{v.get(c, 0.0) / sc:9.3f}" if c in ("hbm_bytes", "l2_hit_rate")
+            else f"{v.get(c, 0.0) / sc:9.1f}" for c, _, sc in cols))
     return "\n".join(lines) + "\n"
 
 

@@ -56,7 +56,7 @@ class CParticles(C.Structure):
 
 class GroupParams(C.Structure):
     _fields_ = [("policy", C.c_int32), ("n_group_max", C.c_int32), ("f", C.c_double),
-                ("chunk", C.c_int32), ("level", C.c_int32)]
+                ("level", C.c_int32)]
 
 
 class Verify(C.Structure):
@@ -306,10 +306,9 @@ class Context:
         self._check(self.L.tree_refit(self.h, C.byref(a)))
 
     def group_ngb_search(self, p: Particles, policy=POLICY_PAPER, n_group_max=32, f=0.5,
-                         chunk=1024, gp_box=None, verify: Verify | None = None, t_cand=1024,
-                         level=0):
+                         gp_box=None, verify: Verify | None = None, t_cand=1024, level=0):
         a = p.c()
-        gp = GroupParams(policy, n_group_max, f, chunk, level)
+        gp = GroupParams(policy, n_group_max, f, level)
         self._check(self.L.group_ngb_search(
             self.h, C.byref(a), None if gp_box is not None else C.byref(gp), _ptr(gp_box),
             C.byref(verify) if verify is not None else None, t_cand))

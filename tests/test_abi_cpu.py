@@ -81,7 +81,7 @@ def test_null_context_is_rejected(lib):
     assert lib.tree_build(None, C.byref(p), None, 8) == S.SFC_EINVAL
     assert lib.tree_refit_hmax(None, C.byref(p)) == S.SFC_EINVAL
     assert lib.tree_refit(None, C.byref(p)) == S.SFC_EINVAL
-    gp = S.GroupParams(1, 8, 0.5, 1024)
+    gp = S.GroupParams(1, 8, 0.5)
     assert lib.group_ngb_search(None, C.byref(p), C.byref(gp), None, None, 1024) == S.SFC_EINVAL
     assert lib.density(None, C.byref(p), C.byref(S.DensityParams()), None) == S.SFC_EINVAL
     assert lib.hydro_force(None, C.byref(p), C.byref(S.HydroParams()), C.byref(S.HydroOut())) == S.SFC_EINVAL

@@ -219,17 +219,25 @@ def test_grouping_hand_case():
     h = np.full(5, 2.0 ** -5)
     B = Boxes.single(5)
     act = np.arange(5)
-    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 64, 0.5, 0)
+    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 64, 0.5)
     assert list(g) == [0, 2, 4, 5]
-    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 1, 0.5, 0)
+    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 1, 0.5)
     assert list(g) == [0, 1, 2, 3, 4, 5]
-    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_COUNT, 2, 0.5, 0)
+    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_COUNT, 2, 0.5)
     assert list(g) == [0, 2, 4, 5]
-    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 64, 0.5, 3)
-    assert list(g) == [0, 2, 3, 5]
     # a larger f swallows the whole line
-    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 64, 4.0, 0)
+    g = oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 64, 4.0)
     assert list(g) == [0, 5]
+    # one pass over the whole active list: 300 actives within R of the first
+    # form one group when the cap allows, and groups of exactly the cap
+    # otherwise (no restarts anywhere along the list)
+    x, y, z = _line(300, 2.0 ** -16)
+    h = np.full(300, 2.0 ** -5)
+    act = np.arange(300)
+    B = Boxes.single(300)
+    assert list(oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 1000, 0.5)) == [0, 300]
+    assert list(oracle.groups(act, x, y, z, h, B, oracle.POLICY_PAPER, 64, 0.5)) == \
+        [0, 64, 128, 192, 256, 300]
 
 
 def test_grouping_uses_first_particle_h():
@@ -237,7 +245,7 @@ def test_grouping_uses_first_particle_h():
     x, y, z = _line(3, 2.0 ** -7)
     h = np.array([2.0 ** -4, 2.0 ** -8, 2.0 ** -8])  # R = 2^-5 from member 0
     g = oracle.groups(np.arange(3), x, y, z, h, Boxes.single(3), oracle.POLICY_PAPER,
-                      64, 0.5, 0)
+                      64, 0.5)
     assert list(g) == [0, 3]
 
 
@@ -247,11 +255,11 @@ def test_grouping_periodic_and_boxes():
     y = z = np.full(2, 0.5)
     h = np.full(2, 2.0 ** -5)
     g = oracle.groups(np.arange(2), x, y, z, h, Boxes.single(2), oracle.POLICY_PAPER,
-                      64, 0.5, 0)
+                      64, 0.5)
     assert list(g) == [0, 2]
     # a box boundary always closes a group
     B = Boxes(np.array([0, 1, 2], np.int64), np.ones(2))
-    g = oracle.groups(np.arange(2), x, y, z, h, B, oracle.POLICY_PAPER, 64, 0.5, 0)
+    g = oracle.groups(np.arange(2), x, y, z, h, B, oracle.POLICY_PAPER, 64, 0.5)
     assert list(g) == [0, 1, 2]
 
 
@@ -259,7 +267,7 @@ def test_grouping_greedy_is_maximal():
     keys, s, B = _rand_sorted(4000, 3)
     act = np.nonzero(np.random.default_rng(1).random(4000) < 0.5)[0]
     f, cap = 0.7, 12
-    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, 1, cap, f, 0)
+    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, 1, cap, f)
     for a, b in zip(g[:-1], g[1:]):
         i0 = act[a]
         assert b - a <= cap
@@ -296,10 +304,10 @@ def test_tree_grouping_hand_case():
         t = oracle.octree(keys, s["x"], s["y"], s["z"], s["h"], B, n_leaf)
         ll = oracle.leaf_levels(t, 8)
         g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, 64, 0.0,
-                          0, level=level, leaf_level=ll)
+                          level=level, leaf_level=ll)
         assert list(g) == want, (n_leaf, level)
     # the cap splits a node's actives
-    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, 3, 0.0, 0,
+    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, 3, 0.0,
                       level=1, leaf_level=oracle.leaf_levels(
                           oracle.octree(keys, s["x"], s["y"], s["z"], s["h"], B, 2), 8))
     assert list(g) == [0, 3, 4, 7, 8]
@@ -325,7 +333,7 @@ def test_tree_grouping_equals_node_ranges(level, n_leaf):
                 assert mem == list(range(mem[0], mem[-1] + 1))
                 want += mem[::cap]
     want = sorted(want) + [len(act)]
-    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, cap, 0.0, 0,
+    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, oracle.POLICY_TREE, cap, 0.0,
                       level=level, leaf_level=oracle.leaf_levels(t, 3000))
     assert list(g) == want
 
@@ -659,7 +667,7 @@ def test_eq1_superset_ratio():
     B = Boxes(w.box_off, w.box_L)
     keys, perm, s = oracle.sorted_state(st, B)
     act = np.arange(w.n)
-    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, 1, 10 ** 6, f, 0)
+    g = oracle.groups(act, s["x"], s["y"], s["z"], s["h"], B, 1, 10 ** 6, f)
     h = w.meta["h"]
     n_ngb = 1 + (w.n - 1) * 4 / 3 * math.pi * h ** 3
     sizes = [oracle.group_superset_size(s["x"], s["y"], s["z"], s["h"], B, act, a, b,
