@@ -292,9 +292,9 @@ def main():
     roof = {"bound": "alu", "achieved": round(ach_ops, 3), "peak": round(peak_t, 2),
             "unit": "T lane-instructions/s", "frac": round(ach_ops / peak_t, 4),
             "traffic": traffic, "kernel": kname,
-            "kernels": ("k_dens_prep + k_walk + k_dgroup + k_dens_solo + k_dsum"
+            "kernels": ("k_dens_prep + k_walk + k_dgrp + k_dens_solo"
                         if kname == "density"
-                        else "refit + k_hydro_prep + k_walk + k_hgroup + k_hydro_solo + k_hsum"),
+                        else "refit + k_hydro_prep + k_walk + k_hgrp + k_hydro_solo"),
             "algorithmic_ops": int(kops),
             "ops_model": f"{TEST_OPS} per member x candidate test, {DENS_PAIR_OPS} per density "
                          f"pair, {HYD_PAIR_OPS} per hydro pair",

@@ -274,6 +274,9 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="lognormal_hydro")
     ap.add_argument("--rounds", type=int, default=2)
+    ap.add_argument("--start", default="",
+                    help="start of the descent instead of the Eq. (1) prior: comma-separated "
+                         "StepConfig fields, e.g. n_leaf=128,n_group_max=24,f=0.5,t_cand=2048")
     ap.add_argument("--bins", default="0",
                     help="timestep bins to tune one after the other (workloads with state['bin']: "
                          "bin b = the particles whose deepest bin is >= b are active)")
@@ -295,6 +298,15 @@ if __name__ == "__main__":
                 w.state = dict(base)
                 w.state["active"] = (base["bin"] >= b).astype(np.uint8)
             print(f"workload {args.workload} bin {b}: {w.n_active} active", flush=True)
-            print("prior", asdict(prior(w)), flush=True)
-            best, c, seen = tune(w, rounds=args.rounds, log=lambda s: print(s, flush=True))
+            start = prior(w)
+            if args.start:
+                kw = {}
+                for item in args.start.split(","):
+                    key, val = item.split("=")
+                    kw[key] = type(getattr(start, key))(float(val) if "." in val else int(val))
+                start = start.with_(**kw)
+                if "t_cand" in kw:
+                    start = start.with_(hydro_t_cand=kw["t_cand"])
+            print("start", asdict(start), flush=True)
+            best, c, seen = tune(w, start, rounds=args.rounds, log=lambda s: print(s, flush=True))
             print("best", asdict(best), c, flush=True)

@@ -201,8 +201,6 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     xb.pos4 = b.take<float4>(n);
     xb.p64 = b.take<double4>(n);
     xb.dstate = b.take<double4>(n);
-    xb.gmask = b.take<uint64_t>(n * (int64_t)(d.t_cand_max / 64));
-    xb.gflag = b.take<uint8_t>(n);
     xb.snap = nullptr;
     xb.drift = nullptr;
     xb.sel = nullptr;

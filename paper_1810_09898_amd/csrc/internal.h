@@ -270,9 +270,6 @@ struct SearchBufs {
     double4 *p64;     // [n] FP64 x, y, z, h: the group filters and the pair terms
     double4 *dstate;  // [n] per active: h, bracket lo, hi, evaluations (members that leave
                       // their group superset)
-    uint64_t *gmask;  // [n * t_cand_max / 64] per active: its neighbour masks over its
-                      // group's candidate chunks (written by the group kernels)
-    uint8_t *gflag;   // [n] per active: 1 = its group computed it (sums from gmask)
     double4 *snap;    // [n] kept supersets: x, y, z (and h) when they were walked, or NULL
     unsigned long long *drift; // [4 + 3 * 512] largest displacement, largest h growth since
                                // (FP64 bits), active particles now, members active now;

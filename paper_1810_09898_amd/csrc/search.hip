@@ -118,6 +118,15 @@ template <> __device__ __forceinline__ double tail_u<double>(double h2, double r
     return q < 1.0 ? 1.0 - q : 0.0;
 }
 
+// square root and reciprocal of the pair arithmetic: the hardware's
+// single-instruction forms (1 ulp) in FP32, the exact ones in FP64
+template <typename T> __device__ __forceinline__ T acc_sqrt(T x);
+template <> __device__ __forceinline__ float acc_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double acc_sqrt<double>(double x) { return sqrt(x); }
+template <typename T> __device__ __forceinline__ T acc_rcp(T x);
+template <> __device__ __forceinline__ float acc_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double acc_rcp<double>(double x) { return 1.0 / x; }
+
 template <typename T> struct Kahan {
     T s = T(0), c = T(0);
     __device__ __forceinline__ void add(T v)
@@ -1244,31 +1253,26 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
     }
 };
 
-// ------------------------------------------------------------------ group scan
-// One wave per group: lane m holds member m.  A filter round tests every
-// member still iterating against the group's superset, KB chunks of 64
-// candidates at a time: each lane loads its candidate's FP64 position once
-// per round, and the members' positions come from their lanes (readlane),
-// so the loads and their address arithmetic are shared by the members.  The
-// test is the canonical FP64 one.  In a group that needs no periodic fold
-// the raw differences are the minimum images, so the test is exact as
-// written; in a group that does, every coordinate is moved into the frame of
-// the group's centre (x - s L, s in {-1, 0, 1} per axis) once, and the test
-// decides on those differences outside a band E = 2^-44 (L h + h^2) around
-// h^2 (the two evaluations differ by less than 2^-48 L h + 2^-50 h^2), and on
-// the canonical r^2 of the raw coordinates inside it.  The neighbour mask of
-// each member over each chunk goes to the member's row of a global mask
-// table, which the per-member sum kernels stream.
-constexpr int KB = 4; // candidate chunks held in registers at a time
-
-struct GrpMembers {
-    int a0, M;       // first position in the active list, member count
-    int i;           // lane m: particle
-    double x, y, z;  // lane m: FP64 position (raw)
-    double sx, sy, sz; // lane m: position in the centre's frame (== raw unless the group wraps)
-    double h;        // lane m: smoothing length
-    double d;        // lane m: |x_i - c|
-};
+// ------------------------------------------------------------------ group workgroups
+// One workgroup of GW waves per group, groups taken from per-XCD work
+// queues.  The group's superset is staged once into LDS: the FP64 positions
+// of its first C candidates, with the mass (density) or h_j and the particle
+// index (hydro); a superset larger than C reads the rest from global memory.
+// Chunks of 64 consecutive candidates lie on the lanes.
+//
+// The membership test is the canonical FP64 one.  In a group that needs no
+// periodic fold the raw differences are the minimum images, so the test is
+// exact as written; in a group that does, every coordinate is moved into
+// the frame of the group's centre (x - s L, s in {-1, 0, 1} per axis), and
+// the test decides on those differences outside a band E = 2^-44 (L h + h^2)
+// around h^2 (the two evaluations differ by less than 2^-48 L h + 2^-50 h^2),
+// and on the canonical r^2 of the raw coordinates inside it.
+constexpr int GW = 4;               // waves per group workgroup
+constexpr int GKB = 2;              // candidate chunks a wave holds during a round
+constexpr int GSTG = 4;             // candidates a thread stages per pass
+constexpr int GC_MAX = 1024;        // staged candidates at most
+constexpr int GMR = 32;             // members whose masks over the staged chunks are kept
+constexpr int GFB_D = 1, GFB_H = 2; // batches a group wave's FIFO hands over at once (density, hydro)
 
 // shift of a coordinate into the frame of the centre c: x - L when it lies
 // more than L/2 above c, x + L when more than L/2 below
@@ -1278,134 +1282,11 @@ __device__ __forceinline__ double to_frame(double x, double c, double L)
     return d >= 0.5 * L ? x - L : (d < -0.5 * L ? x + L : x);
 }
 
-template <bool HYDRO> struct GrpCand {
-    int j[KB];
-    bool v[KB];
-    double x[KB], y[KB], z[KB];
-    double h[KB]; // hydro: h_j
-};
-
-template <bool WRAP, bool HYDRO>
-__device__ __forceinline__ void load_block(const double4 *__restrict__ p64, const int32_t *cg, int nc,
-                                           int cb, int nch, const GSup &s, double L,
-                                           GrpCand<HYDRO> &c)
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int u = 0; u < KB; u++) {
-        const int slot = ((cb + u) << 6) + lane;
-        c.v[u] = slot < nc;
-        c.j[u] = cb + u < nch ? cg[min(slot, nc - 1)] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < KB; u++) {
-        if (cb + u < nch) {
-            const double4 p = p64[c.j[u]];
-            c.x[u] = WRAP ? to_frame(p.x, s.cx, L) : p.x;
-            c.y[u] = WRAP ? to_frame(p.y, s.cy, L) : p.y;
-            c.z[u] = WRAP ? to_frame(p.z, s.cz, L) : p.z;
-            if (HYDRO) c.h[u] = p.w;
-        }
-    }
-}
-
-// One filter round for the members in `ev`: member m's neighbour mask over
-// chunk c goes to rows[m * nchT + c]; lane m returns member m's count.
-// Density: r < h_m.  Hydro: j != i_m and r < max(h_m, h_j).
-template <bool WRAP, bool HYDRO>
-__device__ int group_round(const double4 *__restrict__ p64, const int32_t *cg, const GSup &s,
-                           double L, const GrpMembers &gm, double hm_lane, uint64_t ev,
-                           uint64_t *rows, int nchT, WaveStats &ws)
-{
-    const int lane = lane_id();
-    const int nc = s.nc;
-    const int nch = (nc + 63) >> 6;
-    int cnt = 0;
-    for (int cb = 0; cb < nch; cb += KB) {
-        GrpCand<HYDRO> c;
-        load_block<WRAP, HYDRO>(p64, cg, nc, cb, nch, s, L, c);
-        uint64_t rest = ev;
-        while (rest) {
-            const int m = ctz64(rest);
-            rest &= rest - 1ull;
-            const double xm = uni_d(readlane_d(gm.sx, m)), ym = uni_d(readlane_d(gm.sy, m)),
-                         zm = uni_d(readlane_d(gm.sz, m));
-            const double hmm = uni_d(readlane_d(hm_lane, m));
-            const double h2m = hmm * hmm;
-            const int im = HYDRO ? uni(readlane_i(gm.i, m)) : 0;
-            int sum = 0;
-            uint32_t wlo = 0u, whi = 0u; // lane u: the mask of chunk cb + u
-#pragma unroll
-            for (int u = 0; u < KB; u++) {
-                if (cb + u < nch) {
-                    const double dx = c.x[u] - xm, dy = c.y[u] - ym, dz = c.z[u] - zm;
-                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                    const double hh = HYDRO ? fmax(hmm, c.h[u]) : hmm;
-                    const double lim = HYDRO ? hh * hh : h2m;
-                    bool hit;
-                    if (WRAP) {
-                        const double E = 0x1p-44 * (L * hh + hh * hh);
-                        hit = c.v[u] && r2 < lim - E;
-                        const bool amb = c.v[u] && !hit && r2 <= lim + E;
-                        if (ballot(amb)) {
-                            if (amb) {
-                                // canonical test on the raw coordinates
-                                const double4 p = p64[c.j[u]];
-                                const double rx = uni_d(readlane_d(gm.x, m)),
-                                             ry = uni_d(readlane_d(gm.y, m)),
-                                             rz = uni_d(readlane_d(gm.z, m));
-                                hit = r2_of(p.x, p.y, p.z, rx, ry, rz, L, true) < lim;
-                            }
-                        }
-                    } else {
-                        hit = c.v[u] && r2 < lim;
-                    }
-                    if (HYDRO) hit = hit && c.j[u] != im;
-                    const uint64_t hmask = ballot(hit);
-                    wlo = lane == u ? (uint32_t)hmask : wlo;
-                    whi = lane == u ? (uint32_t)(hmask >> 32) : whi;
-                    sum += popc64(hmask);
-                }
-            }
-            if (lane < KB && cb + lane < nch)
-                rows[(int64_t)m * nchT + cb + lane] = ((uint64_t)whi << 32) | wlo;
-            if (lane == m) cnt += sum;
-        }
-    }
-    ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)nc;
-    return cnt;
-}
-
 __device__ __forceinline__ int wave_sum_i(int v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
-}
-
-// the group's members into the lanes (all of them; `live` marks those that
-// take part: every member, or in a reuse pass those active now)
-__device__ __forceinline__ GrpMembers group_members(const Geom &geo, const GroupArg &ga, int g,
-                                                    const GSup &s, double L, bool wrapf)
-{
-    const int lane = lane_id();
-    GrpMembers gm;
-    gm.a0 = uni(ga.goff[g]);
-    gm.M = min(uni(ga.goff[g + 1]) - gm.a0, 64);
-    gm.i = lane < gm.M ? ga.act[gm.a0 + lane] : 0;
-    gm.x = gm.y = gm.z = gm.h = gm.d = 0.0;
-    if (lane < gm.M) {
-        gm.x = geo.x[gm.i];
-        gm.y = geo.y[gm.i];
-        gm.z = geo.z[gm.i];
-        gm.h = geo.h[gm.i];
-        const double dx = fold(gm.x - s.cx, L), dy = fold(gm.y - s.cy, L), dz = fold(gm.z - s.cz, L);
-        gm.d = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
-    }
-    gm.sx = wrapf ? to_frame(gm.x, s.cx, L) : gm.x;
-    gm.sy = wrapf ? to_frame(gm.y, s.cy, L) : gm.y;
-    gm.sz = wrapf ? to_frame(gm.z, s.cz, L) : gm.z;
-    return gm;
 }
 
 // append the members in `dm` (lanes) to the list of members that finish on
@@ -1419,6 +1300,329 @@ __device__ __forceinline__ void defer_members(uint64_t dm, int a, int32_t *dfr, 
     if ((dm >> lane_id()) & 1ull) dfr[b + mbcnt(dm)] = a;
 }
 
+// LDS of a group workgroup
+struct GLds {
+    double *cx, *cy, *cz; // [C] density: staged candidates' raw FP64 positions (NaN past the superset)
+    uint64_t *rows;       // [GMR][C / 64]: the masks of member m over the staged chunks
+    float *cm;            // [C] density: m_j
+    int32_t *cj;          // [C] hydro: staged candidates' particle index (-1 past the superset)
+    int32_t *mcnt;        // [3][64] density: neighbour counts of member m, round r in r % 3
+    int32_t *ctl;         // [8]: the group taken
+    char *fifo;           // GW FIFOs of 128 * (batches at once) entries
+    int C;
+};
+__host__ __device__ constexpr size_t glds_bytes(int C, bool hydro)
+{
+    return (size_t)C * (hydro ? 4 : 28) + (size_t)8 * GMR * (C / 64) + 3 * 64 * 4 + 8 * 4 +
+           (size_t)GW * 128 * (hydro ? GFB_H : GFB_D) * 4;
+}
+__device__ __forceinline__ GLds glds_carve(char *p, int C, bool hydro)
+{
+    GLds S;
+    S.C = C;
+    S.cx = S.cy = S.cz = nullptr;
+    if (!hydro) {
+        S.cx = (double *)p;
+        p += 8 * (size_t)C;
+        S.cy = (double *)p;
+        p += 8 * (size_t)C;
+        S.cz = (double *)p;
+        p += 8 * (size_t)C;
+    }
+    S.rows = (uint64_t *)p;
+    p += (size_t)8 * GMR * (C / 64);
+    S.cm = hydro ? nullptr : (float *)p;
+    S.cj = hydro ? (int32_t *)p : nullptr;
+    p += 4 * (size_t)C;
+    S.mcnt = (int32_t *)p;
+    p += 3 * 64 * 4;
+    S.ctl = (int32_t *)p;
+    p += 4 * 8;
+    S.fifo = p;
+    return S;
+}
+
+// The group's superset in global memory
+struct GCand {
+    const int32_t *cg; // its candidate indices
+    int nc;
+    const double4 *p64;
+};
+
+// Stage the first min(nc, C) candidates (all threads of the workgroup):
+// density their positions and masses, hydro their particle indices (hydro
+// reads each candidate's record once in its single filter round, so only
+// the index is kept).  The slots past nc up to the end of its chunk get NaN
+// positions (index -1), on which every test fails.  Each pass loads GSTG
+// indices per thread, then their records.
+template <bool HYDRO>
+__device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc, const float *__restrict__ m)
+{
+    const int n = min(gc.nc, S.C);
+    const int npad = min((gc.nc + 63) & ~63, S.C);
+    const double nan = __builtin_nan("");
+    if (HYDRO) {
+        for (int t = (int)threadIdx.x; t < npad; t += GW * 64) S.cj[t] = t < n ? gc.cg[t] : -1;
+        return;
+    }
+    for (int base = 0; base < npad; base += GSTG * GW * 64) {
+        int j[GSTG];
+#pragma unroll
+        for (int u = 0; u < GSTG; u++) {
+            const int t = base + u * GW * 64 + (int)threadIdx.x;
+            j[u] = t < n ? gc.cg[t] : -1;
+        }
+        double4 p[GSTG];
+        float mm[GSTG];
+#pragma unroll
+        for (int u = 0; u < GSTG; u++) {
+            const int jj = j[u] < 0 ? 0 : j[u];
+            p[u] = gc.p64[jj];
+            mm[u] = m[jj];
+        }
+#pragma unroll
+        for (int u = 0; u < GSTG; u++) {
+            const int t = base + u * GW * 64 + (int)threadIdx.x;
+            if (t < npad) {
+                const bool v = j[u] >= 0;
+                S.cx[t] = v ? p[u].x : nan;
+                S.cy[t] = v ? p[u].y : nan;
+                S.cz[t] = v ? p[u].z : nan;
+                S.cm[t] = v ? mm[u] : 0.0f;
+            }
+        }
+    }
+}
+
+// candidate `slot` (one per lane): staged, or from global memory past the
+// staged part; NaN past the superset
+// (the LDS is read unconditionally at a clamped slot, so that the LDS and
+// global paths never merge into one generic pointer)
+__device__ __forceinline__ void cand_xyz(const GLds &S, const GCand &gc, int slot, double &x, double &y,
+                                         double &z)
+{
+    const int sl = min(slot, S.C - 1);
+    x = S.cx[sl];
+    y = S.cy[sl];
+    z = S.cz[sl];
+    if (slot >= S.C) {
+        const bool v = slot < gc.nc;
+        const double4 p = gc.p64[gc.cg[v ? slot : gc.nc - 1]];
+        const double nan = __builtin_nan("");
+        x = v ? p.x : nan;
+        y = v ? p.y : nan;
+        z = v ? p.z : nan;
+    }
+}
+
+// Is the candidate (frame coordinates fx, fy, fz) within sqrt(lim) of the
+// member (frame coordinates xm, ym, zm)?  With WRAP, inside the band E the
+// canonical squared distance of the raw coordinates, raw_r2(), decides.
+template <bool WRAP, class R>
+__device__ __forceinline__ bool in_ball(double fx, double fy, double fz, double xm, double ym,
+                                        double zm, double lim, double E, const R &raw_r2)
+{
+    const double dx = fx - xm, dy = fy - ym, dz = fz - zm;
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    if (!WRAP) return r2 < lim;
+    bool hit = r2 < lim - E;
+    const bool amb = !hit && r2 <= lim + E;
+    if (ballot(amb)) {
+        if (amb) hit = raw_r2() < lim;
+    }
+    return hit;
+}
+
+// hydro candidate `slot`: its particle index (staged, or from global memory
+// past the staged part) and its FP64 record; NaN position and index -1 past
+// the superset
+__device__ __forceinline__ int cand_j(const GLds &S, const GCand &gc, int slot)
+{
+    int j = S.cj[min(slot, S.C - 1)];
+    if (slot >= S.C) j = slot < gc.nc ? gc.cg[slot] : -1;
+    return j;
+}
+__device__ __forceinline__ void cand_rec(const GLds &S, const GCand &gc, int slot, double &x, double &y,
+                                         double &z, double &hj, int &j)
+{
+    j = cand_j(S, gc, slot);
+    const double4 p = gc.p64[j < 0 ? 0 : j];
+    const double nan = __builtin_nan("");
+    x = j < 0 ? nan : p.x;
+    y = j < 0 ? nan : p.y;
+    z = j < 0 ? nan : p.z;
+    hj = j < 0 ? 0.0 : p.w;
+}
+
+// FIFO of a group workgroup's wave: a ring of 128 B entries in LDS; the k-th
+// entry pushed is consumed by lane k % 64, B batches of 64 at a time (their
+// loads in flight together), and each lane adds its terms in push order (the
+// order of FifoB, so both give the same sums).
+template <class E, int B> struct GFifo {
+    static constexpr int RING = 128 * B; // a power of two for B = 1, 2, 4
+    E *buf;
+    int head, np; // ring position of the oldest entry (a multiple of 64), entries held
+    template <class F> __device__ __forceinline__ void run(F &f, int cnt)
+    {
+        const int lane = lane_id();
+        typename F::Term t[B];
+        bool v[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            const int idx = (b << 6) + lane;
+            v[b] = idx < cnt;
+            if ((b << 6) < cnt) t[b] = f.term(v[b] ? buf[(head + idx) & (RING - 1)] : E{0});
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            if ((b << 6) < cnt && v[b]) f.add(t[b]);
+    }
+    // push entry e of every lane set in the (uniform) mask mk
+    template <class F> __device__ __forceinline__ void push(uint64_t mk, const E &e, F &f)
+    {
+        if (!mk) return;
+        if ((mk >> lane_id()) & 1ull) buf[(head + np + mbcnt(mk)) & (RING - 1)] = e;
+        np = uni(np + popc64(mk));
+        if (np >= 64 * B) {
+            wave_lds_sync();
+            run(f, 64 * B);
+            head = uni((head + 64 * B) & (RING - 1));
+            np -= 64 * B;
+            wave_lds_sync();
+        }
+    }
+    template <class F> __device__ __forceinline__ void flush(F &f)
+    {
+        wave_lds_sync();
+        if (np > 0) run(f, np);
+        np = 0;
+        head = 0;
+        wave_lds_sync();
+    }
+};
+
+// The members of a group in the lanes of every wave of its workgroup (each
+// wave loads them; lane m holds member m)
+struct GMem {
+    double rx, ry, rz; // raw position
+    double h;          // density: h of the current round
+    double d;          // distance to the group centre (density: plus the drift)
+    int i;             // particle
+    bool live;         // takes part (a reuse pass: active now)
+};
+__device__ __forceinline__ GMem grp_members(const Geom &geo, const GroupArg &ga, const uint8_t *active,
+                                            int a0, int M, const GSup &s, double L, double dl)
+{
+    const int lane = lane_id();
+    GMem gm;
+    gm.live = lane < M;
+    gm.i = 0;
+    gm.rx = gm.ry = gm.rz = gm.h = gm.d = 0.0;
+    if (gm.live) {
+        gm.i = ga.act[a0 + lane];
+        gm.rx = geo.x[gm.i];
+        gm.ry = geo.y[gm.i];
+        gm.rz = geo.z[gm.i];
+        gm.h = geo.h[gm.i];
+        if (active) gm.live = active[gm.i] != 0; // reuse: the members active now
+        const double dx = fold(gm.rx - s.cx, L), dy = fold(gm.ry - s.cy, L), dz = fold(gm.rz - s.cz, L);
+        gm.d = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx))) + dl;
+    }
+    return gm;
+}
+
+// One filter round (all waves of the workgroup) of the members in `ev`: wave
+// w takes blocks w, w + GW, ... of GKB chunks, holds their candidates in
+// registers and tests them against every member of ev (member data from
+// lane m by readlane).  Member m's mask over staged chunk c goes to
+// S.rows[m * (C / 64) + c] (m < GMR); density adds the counts to cnt[m].
+// Density: r < h_m; hydro: r < max(h_m, h_j) and j != i_m.
+template <bool WRAP, bool HYDRO>
+__device__ __forceinline__ void grp_round(const GLds &S, const GCand &gc, const GSup &s, double L,
+                                          uint64_t ev, const GMem &gm, int32_t *cnt_m)
+{
+    const int lane = lane_id();
+    const int wv = uni((int)(threadIdx.x >> 6));
+    const int nch = (gc.nc + 63) >> 6;
+    const int RC = S.C >> 6;
+    const double xm = WRAP ? to_frame(gm.rx, s.cx, L) : gm.rx;
+    const double ym = WRAP ? to_frame(gm.ry, s.cy, L) : gm.ry;
+    const double zm = WRAP ? to_frame(gm.rz, s.cz, L) : gm.rz;
+    const double limv = gm.h * gm.h;
+    const double Ev = (WRAP && !HYDRO) ? 0x1p-44 * (L * gm.h + gm.h * gm.h) : 0.0;
+    int cntv = 0;
+    for (int cb = wv * GKB; cb < nch; cb += GW * GKB) {
+        double x[GKB], y[GKB], z[GKB], hj[GKB];
+        int jj[GKB];
+#pragma unroll
+        for (int u = 0; u < GKB; u++) {
+            if (cb + u < nch) {
+                const int slot = ((cb + u) << 6) + lane;
+                if (HYDRO)
+                    cand_rec(S, gc, slot, x[u], y[u], z[u], hj[u], jj[u]);
+                else
+                    cand_xyz(S, gc, slot, x[u], y[u], z[u]);
+                if (WRAP) {
+                    x[u] = to_frame(x[u], s.cx, L);
+                    y[u] = to_frame(y[u], s.cy, L);
+                    z[u] = to_frame(z[u], s.cz, L);
+                }
+            }
+        }
+        uint64_t rest = ev;
+        while (rest) {
+            const int m = ctz64(rest);
+            rest &= rest - 1ull;
+            const double xmm = readlane_d(xm, m), ymm = readlane_d(ym, m), zmm = readlane_d(zm, m);
+            const double lim = HYDRO ? 0.0 : readlane_d(limv, m);
+            const double E = (WRAP && !HYDRO) ? readlane_d(Ev, m) : 0.0;
+            const double hmm = HYDRO ? readlane_d(gm.h, m) : 0.0;
+            const int imm = HYDRO ? readlane_i(gm.i, m) : 0;
+            int cnt = 0;
+#pragma unroll
+            for (int u = 0; u < GKB; u++) {
+                if (cb + u < nch) {
+                    const int slot = ((cb + u) << 6) + lane;
+                    auto raw = [&]() {
+                        double px, py, pz, ph;
+                        int pj;
+                        if (HYDRO)
+                            cand_rec(S, gc, slot, px, py, pz, ph, pj);
+                        else
+                            cand_xyz(S, gc, slot, px, py, pz);
+                        return r2_of(px, py, pz, readlane_d(gm.rx, m), readlane_d(gm.ry, m),
+                                     readlane_d(gm.rz, m), L, true);
+                    };
+                    bool hit;
+                    if (HYDRO) {
+                        const double hh = fmax(hmm, hj[u]);
+                        const double Eu = WRAP ? 0x1p-44 * (L * hh + hh * hh) : 0.0;
+                        hit = in_ball<WRAP>(x[u], y[u], z[u], xmm, ymm, zmm, hh * hh, Eu, raw) &&
+                              jj[u] != imm;
+                    } else {
+                        hit = in_ball<WRAP>(x[u], y[u], z[u], xmm, ymm, zmm, lim, E, raw);
+                    }
+                    const uint64_t mk = ballot(hit);
+                    if (!HYDRO) cnt += popc64(mk);
+                    if (m < GMR && cb + u < RC && lane == 0) S.rows[m * RC + cb + u] = mk;
+                }
+            }
+            if (!HYDRO) cntv += lane == m ? cnt : 0;
+        }
+    }
+    if (!HYDRO && ((ev >> lane) & 1ull)) atomicAdd(&cnt_m[lane], cntv);
+}
+
+// the group taken by the workgroup (wave 0 takes it; -1: none left)
+__device__ __forceinline__ int wg_take(Queue &q, const GLds &S)
+{
+    if (threadIdx.x < 64) {
+        const int g = queue_next(q);
+        if (threadIdx.x == 0) S.ctl[0] = g;
+    }
+    __syncthreads();
+    return uni(S.ctl[0]);
+}
 } // namespace
 
 // ================================================================== density
@@ -1437,16 +1641,13 @@ struct DensK {
     const uint8_t *active;           // reused supersets: the members computed now
     int32_t *dfr;                    // members that finish on their own (st->n_dfr of them)
     double4 *dstate;                 // per active: h, bracket lo, hi and evaluations so far
-    uint64_t *gmask;                 // per active: neighbour masks over its group's chunks
-    uint8_t *gflag;                  // per active: 1 = finished in its group (sums from gmask)
-    int n_ngb, dn, max_iter, fixed_h, nchT;
+    int n_ngb, dn, max_iter, fixed_h;
+    int C;                           // candidates a group workgroup stages in LDS
 };
 
 namespace {
 
-template <int KER, typename ACC> struct DensPair {
-    const double4 *p64;
-    const float *m;
+template <int KER, typename ACC> struct DensAcc {
     double xi, yi, zi, L;
     bool wrap;
     double h2;
@@ -1455,16 +1656,26 @@ template <int KER, typename ACC> struct DensPair {
     struct Term {
         ACC w, d;
     };
-    __device__ __forceinline__ Term term(const DEnt &e) const
+    __device__ __forceinline__ void init(double x, double y, double z, double Lb, double h, bool wr)
     {
-        const int j = e.j;
-        const double4 pj = p64[j];
-        // the canonical FP64 r^2 of the pair, rounded once for the FP32 sums
-        const double r2 = r2_of(pj.x, pj.y, pj.z, xi, yi, zi, L, wrap);
-        const ACC q = sqrt((ACC)r2) * hinv;
+        xi = x;
+        yi = y;
+        zi = z;
+        L = Lb;
+        wrap = wr;
+        h2 = h * h;
+        hinv = (ACC)(1.0 / h);
+        inv_h2 = (ACC)(1.0 / (h * h));
+    }
+    // the pair term from the neighbour's FP64 position and mass: the
+    // canonical FP64 r^2 of the pair, rounded once for the FP32 sums
+    __device__ __forceinline__ Term make(double xj, double yj, double zj, float mjf) const
+    {
+        const double r2 = r2_of(xj, yj, zj, xi, yi, zi, L, wrap);
+        const ACC q = acc_sqrt((ACC)r2) * hinv;
         ACC w, dw;
         kern_eval_u<KER, ACC>(q, tail_u<ACC>(h2, r2, inv_h2, q), w, dw);
-        ACC mj = (ACC)m[j];
+        const ACC mj = (ACC)mjf;
         Term t;
         t.w = mj * w;
         t.d = mj * mad(q, dw, ACC(3) * w);
@@ -1477,27 +1688,56 @@ template <int KER, typename ACC> struct DensPair {
     }
 };
 
+// neighbours given by particle index
+template <int KER, typename ACC> struct DensPair : DensAcc<KER, ACC> {
+    using Term = typename DensAcc<KER, ACC>::Term;
+    const double4 *p64;
+    const float *m;
+    __device__ __forceinline__ Term term(const DEnt &e) const
+    {
+        const double4 pj = p64[e.j];
+        return this->make(pj.x, pj.y, pj.z, m[e.j]);
+    }
+};
+
+// neighbours given by their slot in a staged group superset
+template <int KER, typename ACC> struct DensPairS : DensAcc<KER, ACC> {
+    using Term = typename DensAcc<KER, ACC>::Term;
+    GLds S;
+    GCand gc;
+    const float *m;
+    __device__ __forceinline__ Term term(const DEnt &e) const
+    {
+        const int s = e.j;
+        const int sl = min(s, S.C - 1);
+        double xj = S.cx[sl], yj = S.cy[sl], zj = S.cz[sl];
+        float mj = S.cm[sl];
+        if (s >= S.C) {
+            const int j = gc.cg[s];
+            const double4 pj = gc.p64[j];
+            xj = pj.x;
+            yj = pj.y;
+            zj = pj.z;
+            mj = m[j];
+        }
+        return this->make(xj, yj, zj, mj);
+    }
+};
+
 template <int KER, typename ACC>
 __device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, double xi, double yi,
                                                         double zi, double L, double h, bool wrap)
 {
     DensPair<KER, ACC> pp;
+    pp.init(xi, yi, zi, L, h, wrap);
     pp.p64 = k.p64;
     pp.m = k.m;
-    pp.xi = xi;
-    pp.yi = yi;
-    pp.zi = zi;
-    pp.L = L;
-    pp.wrap = wrap;
-    pp.h2 = h * h;
-    pp.hinv = (ACC)(1.0 / h);
-    pp.inv_h2 = (ACC)(1.0 / (h * h));
     return pp;
 }
 
 // the sums of particle i at its final h: rho, drho/dh, f
-template <int KER, typename ACC>
-__device__ void dens_write_sums(const DensK &k, int i, double h, const DensPair<KER, ACC> &pp)
+template <int KER, typename ACC, class P>
+__device__ void dens_write_sums(const DensK &k, int i, double h, const P &pp)
 {
     double Sw = (double)wave_sum_f_or_d(pp.sw.value());
     double Sd = (double)wave_sum_f_or_d(pp.sd.value());
@@ -1515,9 +1755,9 @@ __device__ void dens_write_sums(const DensK &k, int i, double h, const DensPair<
     if (k.out.fgrad64) k.out.fgrad64[i] = f;
 }
 
-template <int KER, typename ACC>
+template <int KER, typename ACC, class P>
 __device__ void dens_write(const DensK &k, int i, double h, int nn, int it, bool conv,
-                           const DensPair<KER, ACC> &pp, WaveStats &ws)
+                           const P &pp, WaveStats &ws)
 {
     ws.iters += (uint32_t)it;
     ws.pairs += (unsigned)nn;
@@ -1631,140 +1871,149 @@ __device__ __forceinline__ bool own_superset(const DensK &k, const MemLds &S, Me
 
 constexpr int ST_ITER = 0, ST_DONE = 1, ST_DEFER = 2;
 
-// The h loop of one group's members on its superset: every member still
-// iterating is counted in the same round; members that finish write h and
-// their counts and keep their last masks for k_dsum; members whose h
-// outgrows the superset (or whose group kept none) are listed for
-// k_dens_solo with the state they reached.
-template <bool WRAP>
-__device__ void dens_count(const DensK &k, int g, const GSup &s, const BoxInfo &bx, double dl,
-                           WaveStats &ws)
+// Member m's neighbours (one wave): its masks of the last round (re-tested
+// for members past GMR and chunks past the staged ones) pushed in candidate
+// order through the wave's FIFO into the sums.  Returns the neighbour count.
+template <int KER, typename ACC, bool WRAP>
+__device__ __forceinline__ int dens_emit(const DensK &k, const GLds &S, const GCand &gc, const GSup &s,
+                                         double L, bool wrap, const GMem &gm, int m, DEnt *fifo)
 {
     const int lane = lane_id();
-    const GrpMembers gm = group_members(k.g, k.ga, g, s, bx.L, WRAP);
-    bool live = lane < gm.M;
-    if (k.active && live) live = k.active[gm.i] != 0; // reuse: the members active now
-    const uint64_t livem = ballot(live);
-    // a reused superset: every particle may have moved by dl since the walk
-    const double d = gm.d + dl;
-    double h = gm.h, lo = 0.0, hi = INFINITY;
-    int it = 0, nn = 0, stt = live ? ST_ITER : ST_DONE;
-    bool conv = false;
-    if (s.flags & GSUP_SOLO) stt = live ? ST_DEFER : stt;
-    const int32_t *cg = k.ca.cand + s.c0;
-    uint64_t *rows = k.gmask + (int64_t)gm.a0 * k.nchT;
-    for (int round = 0; livem && round <= k.max_iter; round++) {
-        const bool over = stt == ST_ITER && !(h + d <= s.cov);
-        if (over) stt = ST_DEFER;
-        const uint64_t ev = ballot(stt == ST_ITER);
-        if (!ev) break;
-        const int cnt = group_round<WRAP, false>(k.p64, cg, s, bx.L, gm, h, ev, rows, k.nchT, ws);
-        if ((ev >> lane) & 1ull) {
-            it++;
-            nn = cnt;
-            if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
-                conv = true;
-                stt = ST_DONE;
-            } else if (it >= k.max_iter) {
-                stt = ST_DONE;
-            } else {
-                h = h_step(nn, k.n_ngb, k.dn, h, lo, hi);
-            }
+    const double rx = uni_d(readlane_d(gm.rx, m)), ry = uni_d(readlane_d(gm.ry, m)),
+                 rz = uni_d(readlane_d(gm.rz, m));
+    const double h = uni_d(readlane_d(gm.h, m));
+    const double lim = h * h;
+    const double E = WRAP ? 0x1p-44 * (L * h + h * h) : 0.0;
+    const double xm = WRAP ? to_frame(rx, s.cx, L) : rx;
+    const double ym = WRAP ? to_frame(ry, s.cy, L) : ry;
+    const double zm = WRAP ? to_frame(rz, s.cz, L) : rz;
+    DensPairS<KER, ACC> pp;
+    pp.init(rx, ry, rz, L, h, wrap);
+    pp.S = S;
+    pp.gc = gc;
+    pp.m = k.m;
+    GFifo<DEnt, GFB_D> q{fifo, 0, 0};
+    const int nch = (gc.nc + 63) >> 6;
+    const int RC = S.C >> 6;
+    int nn = 0;
+    for (int c = 0; c < nch; c++) {
+        const int slot = (c << 6) + lane;
+        uint64_t mk;
+        if (m < GMR && c < RC) {
+            mk = uni_u64(S.rows[m * RC + c]);
+        } else {
+            double x, y, z;
+            cand_xyz(S, gc, slot, x, y, z);
+            const double fx = WRAP ? to_frame(x, s.cx, L) : x;
+            const double fy = WRAP ? to_frame(y, s.cy, L) : y;
+            const double fz = WRAP ? to_frame(z, s.cz, L) : z;
+            mk = ballot(in_ball<WRAP>(fx, fy, fz, xm, ym, zm, lim, E,
+                                      [&]() { return r2_of(x, y, z, rx, ry, rz, L, true); }));
         }
+        nn += popc64(mk);
+        q.push(mk, DEnt{slot}, pp);
     }
-    const uint64_t dm = ballot(live && stt == ST_DEFER);
-    if ((dm >> lane) & 1ull) k.dstate[gm.a0 + lane] = make_double4(h, lo, hi, (double)it);
-    defer_members(dm, gm.a0 + lane, k.dfr, k.st);
-    ws.deferred += (uint32_t)popc64(dm);
-    const bool done = live && stt == ST_DONE;
-    if (done) {
-        k.g.h[gm.i] = h;
-        if (k.out.nngb) k.out.nngb[gm.i] = nn;
-        if (k.out.iters) k.out.iters[gm.i] = it;
-        if (k.out.converged) k.out.converged[gm.i] = conv ? 1 : 0;
-    }
-    if (lane < gm.M) k.gflag[gm.a0 + lane] = done ? 1 : 0;
-    ws.iters += (uint32_t)uni(wave_sum_i(done ? it : 0));
-    ws.not_conv += (uint32_t)popc64(ballot(done && !conv));
+    q.flush(pp);
+    dens_write_sums<KER, ACC>(k, uni(readlane_i(gm.i, m)), h, pp);
+    return nn;
 }
-
-// stream the neighbours of a member's mask row (in global memory) through
-// the FIFO
-template <class F, class Q, class E>
-__device__ __forceinline__ void stream_row(const int32_t *cand, int64_t c0, int nc,
-                                           const uint64_t *row, Q &q, F &consume, int &nn)
-{
-    const int lane = lane_id();
-    const int nch = (nc + 63) >> 6;
-    const int32_t *cg = cand + c0;
-    for (int s0 = 0; s0 < nch; s0 += 64) {
-        const uint64_t rv = s0 + lane < nch ? row[s0 + lane] : 0ull;
-        const int ns = min(64, nch - s0);
-        for (int cb = 0; cb < ns; cb += UNR) {
-            uint64_t mk[UNR];
-            int j[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                mk[u] = cb + u < ns ? readlane_u64(rv, cb + u) : 0ull;
-                j[u] = mk[u] ? cg[min(((s0 + cb + u) << 6) + lane, nc - 1)] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                nn += popc64(mk[u]);
-                q.push((mk[u] >> lane) & 1ull, E{j[u]}, consume);
-            }
-        }
-    }
-    q.flush(consume);
-}
-
 } // namespace
 
-// One wave per group, groups taken from per-XCD work queues: the group's
-// members iterate h together on its superset; members that outgrow it are
-// listed for k_dens_solo.
-__global__ __launch_bounds__(64) void k_dgroup(DensK k)
-{
-    const int G = uni(*k.ga.n_groups);
-    Queue wq = queue_open(k.st->qctr2, G);
-    WaveStats ws;
-    const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
-    for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
-        const GSup s = load_gsup(k.ca.sup + g);
-        const BoxInfo bx = box_info(k.g, uni(k.ga.act[uni(k.ga.goff[g])]));
-        // a reused superset: positions moved since the walk, pairs may fold
-        if ((s.flags & GSUP_WRAP) || k.drift)
-            dens_count<true>(k, g, s, bx, dl, ws);
-        else
-            dens_count<false>(k, g, s, bx, dl, ws);
-    }
-    ws.flush(k.st);
-}
-
-// One wave per member that finished in its group: the density sums over the
-// neighbours its mask row holds.
-template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_dsum(DensK k)
+// Density, one workgroup per group: the members iterate h together on the
+// staged superset, one filter round at a time.  Every wave keeps the
+// members' h loop state in its lanes and applies the same h step after each
+// round (the round's counts are read from LDS after the one barrier of the
+// round; counts of round r go to buffer r % 3, so a buffer is cleared two
+// rounds after it was read).  Members whose h outgrows the superset, or
+// whose group kept none, are listed for k_dens_solo with the state they
+// reached; every member that finished is then streamed by one wave into its
+// sums from its masks of the last round.
+template <int KER, typename ACC>
+__global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_dgrp(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    DEnt *fifo = (DEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
-    const int A = uni(*k.ga.n_act);
-    const ItemRange ar = item_range(A);
+    const GLds S = glds_carve(lds_raw, k.C, false);
+    const int lane = lane_id();
+    const int wv = uni((int)(threadIdx.x >> 6));
+    DEnt *fifo = (DEnt *)(S.fifo + (size_t)wv * 128 * GFB_D * sizeof(DEnt));
+    Queue wq = queue_open(k.st->qctr2, uni(*k.ga.n_groups));
     WaveStats ws;
-    for (int a = ar.i; a < ar.end; a += ar.stride) {
-        if (!uni(k.gflag[a])) continue;
-        const int i = uni(k.ga.act[a]);
-        const GSup s = load_gsup(k.ca.sup + uni(k.ca.grp[a]));
-        const BoxInfo bx = box_info(k.g, i);
-        const double h = uni_d(k.g.h[i]);
+    // a reused superset: every particle may have moved by dl since the walk
+    const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
+    for (;;) {
+        const int g = wg_take(wq, S);
+        if (g < 0) break;
+        const GSup s = load_gsup(k.ca.sup + g);
+        const int a0 = uni(k.ga.goff[g]);
+        const int M = min(uni(k.ga.goff[g + 1]) - a0, 64);
+        const BoxInfo bx = box_info(k.g, uni(k.ga.act[a0]));
         const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
-        DensPair<KER, ACC> pp = dens_pair<KER, ACC>(k, uni_d(k.g.x[i]), uni_d(k.g.y[i]),
-                                                    uni_d(k.g.z[i]), bx.L, h, wrap);
-        Fifo q{fifo, 0};
-        int nn = 0;
-        stream_row<DensPair<KER, ACC>, Fifo, DEnt>(k.ca.cand, s.c0, s.nc, k.gmask + (int64_t)a * k.nchT,
-                                                   q, pp, nn);
-        ws.pairs += (unsigned)nn;
-        dens_write_sums<KER, ACC>(k, i, h, pp);
+        const GCand gc{k.ca.cand + s.c0, s.nc, k.p64};
+        GMem gm = grp_members(k.g, k.ga, k.active, a0, M, s, bx.L, dl);
+        int it = 0, nn = 0;
+        int stt = gm.live ? ((s.flags & GSUP_SOLO) ? ST_DEFER : ST_ITER) : ST_DONE;
+        if (stt == ST_ITER && !(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
+        double lo = 0.0, hi = INFINITY;
+        bool conv = false;
+        if (wv == 0) {
+            S.mcnt[lane] = 0;
+            S.mcnt[64 + lane] = 0;
+        }
+        if (!(s.flags & GSUP_SOLO)) stage_cands<false>(S, gc, k.m);
+        __syncthreads();
+        for (int round = 0; round <= k.max_iter; round++) {
+            const uint64_t ev = ballot(stt == ST_ITER);
+            if (!ev) break;
+            int32_t *cnt = S.mcnt + 64 * (round % 3);
+            if (wv == 0) S.mcnt[64 * ((round + 1) % 3) + lane] = 0;
+            if (wrap)
+                grp_round<true, false>(S, gc, s, bx.L, ev, gm, cnt);
+            else
+                grp_round<false, false>(S, gc, s, bx.L, ev, gm, cnt);
+            __syncthreads();
+            if (wv == 0) ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)s.nc;
+            if ((ev >> lane) & 1ull) {
+                it++;
+                nn = cnt[lane];
+                if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
+                    conv = true;
+                    stt = ST_DONE;
+                } else if (it >= k.max_iter) {
+                    stt = ST_DONE;
+                } else {
+                    gm.h = h_step(nn, k.n_ngb, k.dn, gm.h, lo, hi);
+                    if (!(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
+                }
+            }
+        }
+        const bool done = gm.live && stt == ST_DONE;
+        if (wv == 0) {
+            // a member still iterating here has hit the round limit: impossible
+            // while every round advances it, kept as a guard
+            if (ballot(stt == ST_ITER)) guard_hit(k.st);
+            const uint64_t dm = ballot(gm.live && stt == ST_DEFER);
+            if ((dm >> lane) & 1ull) k.dstate[a0 + lane] = make_double4(gm.h, lo, hi, (double)it);
+            defer_members(dm, a0 + lane, k.dfr, k.st);
+            ws.deferred += (uint32_t)popc64(dm);
+            if (done) {
+                k.g.h[gm.i] = gm.h;
+                if (k.out.nngb) k.out.nngb[gm.i] = nn;
+                if (k.out.iters) k.out.iters[gm.i] = it;
+                if (k.out.converged) k.out.converged[gm.i] = conv ? 1 : 0;
+            }
+            ws.iters += (uint32_t)uni(wave_sum_i(done ? it : 0));
+            ws.not_conv += (uint32_t)popc64(ballot(done && !conv));
+        }
+        // the r-th member that finished is streamed by wave r mod GW
+        uint64_t rest = ballot(done);
+        for (int r = 0; rest; r++) {
+            const int m = ctz64(rest);
+            rest &= rest - 1ull;
+            if (r % GW != wv) continue;
+            const int c = wrap ? dens_emit<KER, ACC, true>(k, S, gc, s, bx.L, wrap, gm, m, fifo)
+                               : dens_emit<KER, ACC, false>(k, S, gc, s, bx.L, wrap, gm, m, fifo);
+            ws.pairs += (unsigned long long)c;
+        }
     }
     ws.flush(k.st);
 }
@@ -1822,16 +2071,14 @@ struct HydroK {
     const unsigned long long *drift; // reused supersets: largest displacement, h growth, or NULL
     const uint8_t *active;           // reused supersets: the members computed now
     int32_t *dfr;                    // members that walk alone (st->n_dfr of them)
-    uint64_t *gmask;                 // per active: neighbour masks over its group's chunks
-    uint8_t *gflag;                  // per active: 1 = filtered in its group (sums from gmask)
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
-    int nchT;
+    int C; // candidates a group workgroup stages in LDS
 };
 
 namespace {
-template <int KER, typename ACC> struct HydroPair {
+template <int KER, typename ACC> struct HydroAcc {
     const HydroK *k;
     double xi, yi, zi, L;
     bool wrap;
@@ -1842,12 +2089,11 @@ template <int KER, typename ACC> struct HydroPair {
     struct Term {
         ACC ax, ay, az, du, vs;
     };
-    __device__ __forceinline__ Term term(const HEnt &e) const
+    // the pair term of neighbour j with FP64 position and h pj
+    __device__ __forceinline__ Term make(int j, const double4 &pj) const
     {
         constexpr ACC C = (ACC)knorm<KER>();
-        const int j = e.j;
         // x_i - x_j (the force direction) in FP64, rounded once for FP32
-        const double4 pj = k->p64[j];
         double dxd = xi - pj.x, dyd = yi - pj.y, dzd = zi - pj.z;
         if (wrap) {
             dxd = fold(dxd, L);
@@ -1880,12 +2126,12 @@ template <int KER, typename ACC> struct HydroPair {
             csj = (ACC)b.z;
             hj = (ACC)b.w;
         }
-        ACC r = sqrt((ACC)r2d);
-        ACC rinv = r > ACC(0) ? ACC(1) / r : ACC(0);
+        ACC r = acc_sqrt((ACC)r2d);
+        ACC rinv = r > ACC(0) ? acc_rcp(r) : ACC(0);
         ACC w, dwi, dwj;
         const ACC qi = r * hinv;
         kern_eval_u<KER, ACC>(qi, tail_u<ACC>(h2, r2d, hinv * hinv, qi), w, dwi);
-        ACC hjinv = ACC(1) / hj;
+        ACC hjinv = acc_rcp(hj);
         const ACC qj = r * hjinv;
         kern_eval_u<KER, ACC>(qj, tail_u<ACC>(pj.w * pj.w, r2d, hjinv * hjinv, qj), w, dwj);
         ACC hj2 = hjinv * hjinv;
@@ -1896,7 +2142,7 @@ template <int KER, typename ACC> struct HydroPair {
         ACC vr = mad(vdz, dz, mad(vdy, dy, vdx * dx));
         ACC wij = vr < ACC(0) ? vr * rinv : ACC(0);
         ACC vsig = cs + csj - ACC(3) * wij;
-        ACC visc = -(ACC)k->alpha * vsig * wij / (rho + rhoj);
+        ACC visc = -(ACC)k->alpha * vsig * wij * acc_rcp(rho + rhoj);
         ACC fac = mj * (pf * dWi + pfj * dWj + visc * dWb);
         ACC fr = fac * rinv;
         Term t;
@@ -1915,6 +2161,50 @@ template <int KER, typename ACC> struct HydroPair {
         du.add(t.du);
         vmax = t.vs > vmax ? t.vs : vmax;
     }
+    __device__ __forceinline__ void init(const HydroK &kk, int i, double x, double y, double z,
+                                         double Lb, double h, bool wr)
+    {
+        k = &kk;
+        xi = x;
+        yi = y;
+        zi = z;
+        L = Lb;
+        wrap = wr;
+        double hv = 1.0 / h;
+        h2 = h * h;
+        hinv = (ACC)hv;
+        hinv4 = (ACC)(hv * hv * hv * hv);
+        vx = (ACC)kk.vx[i];
+        vy = (ACC)kk.vy[i];
+        vz = (ACC)kk.vz[i];
+        rho = (ACC)kk.rho[i];
+        double gm1 = kk.gamma - 1.0;
+        double u = kk.u[i];
+        pf = (ACC)(kk.fgrad[i] * gm1 * u / (double)kk.rho[i]);
+        cs = (ACC)sqrt(kk.gamma * gm1 * u);
+        vmax = ACC(0);
+    }
+};
+
+// neighbours given by particle index
+template <int KER, typename ACC> struct HydroPair : HydroAcc<KER, ACC> {
+    using Term = typename HydroAcc<KER, ACC>::Term;
+    __device__ __forceinline__ Term term(const HEnt &e) const
+    {
+        return this->make(e.j, this->k->p64[e.j]);
+    }
+};
+
+// neighbours given by their slot in a staged group superset
+template <int KER, typename ACC> struct HydroPairS : HydroAcc<KER, ACC> {
+    using Term = typename HydroAcc<KER, ACC>::Term;
+    GLds S;
+    GCand gc;
+    __device__ __forceinline__ Term term(const HEnt &e) const
+    {
+        const int j = cand_j(S, gc, e.j);
+        return this->make(j, gc.p64[j]);
+    }
 };
 
 template <int KER, typename ACC>
@@ -1922,30 +2212,12 @@ __device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, int i
                                                           double zi, double L, double h, bool wrap)
 {
     HydroPair<KER, ACC> hp;
-    hp.k = &k;
-    hp.xi = xi;
-    hp.yi = yi;
-    hp.zi = zi;
-    hp.L = L;
-    hp.wrap = wrap;
-    double hinv = 1.0 / h;
-    hp.h2 = h * h;
-    hp.hinv = (ACC)hinv;
-    hp.hinv4 = (ACC)(hinv * hinv * hinv * hinv);
-    hp.vx = (ACC)k.vx[i];
-    hp.vy = (ACC)k.vy[i];
-    hp.vz = (ACC)k.vz[i];
-    hp.rho = (ACC)k.rho[i];
-    double gm1 = k.gamma - 1.0;
-    double u = k.u[i];
-    hp.pf = (ACC)(k.fgrad[i] * gm1 * u / (double)k.rho[i]);
-    hp.cs = (ACC)sqrt(k.gamma * gm1 * u);
-    hp.vmax = ACC(0);
+    hp.init(k, i, xi, yi, zi, L, h, wrap);
     return hp;
 }
 
-template <int KER, typename ACC>
-__device__ void hydro_write(const HydroK &k, int i, const HydroPair<KER, ACC> &hp)
+template <int KER, typename ACC, class P>
+__device__ void hydro_write(const HydroK &k, int i, const P &hp)
 {
     double ax = (double)wave_sum_f_or_d(hp.ax.value());
     double ay = (double)wave_sum_f_or_d(hp.ay.value());
@@ -1969,31 +2241,54 @@ __device__ void hydro_write(const HydroK &k, int i, const HydroPair<KER, ACC> &h
     if (k.out.dudt64) k.out.dudt64[i] = du;
 }
 
-// The hydro filter of one group: one round for the members its superset
-// covers; their masks go to their rows for k_hsum, the others are listed
-// for k_hydro_solo.
-template <bool WRAP>
-__device__ void hydro_filter(const HydroK &k, int g, const GSup &s, const BoxInfo &bx, double dl,
-                             double dh, WaveStats &ws)
+// Member m's hydro neighbours (one wave): its masks of the filter round
+// (re-tested for members past GMR and chunks past the staged ones) pushed
+// in candidate order through the wave's FIFO into the force sums.  Returns
+// the neighbour count.
+template <int KER, typename ACC, bool WRAP>
+__device__ __forceinline__ int hydro_emit(const HydroK &k, const GLds &S, const GCand &gc, const GSup &s,
+                                          double L, bool wrap, const GMem &gm, int m, HEnt *fifo)
 {
     const int lane = lane_id();
-    const GrpMembers gm = group_members(k.g, k.ga, g, s, bx.L, WRAP);
-    bool live = lane < gm.M;
-    if (k.active && live) live = k.active[gm.i] != 0; // reuse: the members active now
-    const uint64_t livem = ballot(live);
-    // a reused superset still covers a member while its sphere, grown by
-    // the drift, stays inside the walked ball (and its radius for h_j)
-    const bool kept = !k.drift || (gm.h + gm.d + dl <= s.cov && gm.d + dl + dh <= s.rs);
-    const uint64_t dm = (s.flags & GSUP_SOLO) ? livem : ballot(live && !kept);
-    defer_members(dm, gm.a0 + lane, k.dfr, k.st);
-    ws.deferred += (uint32_t)popc64(dm);
-    const uint64_t ev = livem & ~dm;
-    if (lane < gm.M) k.gflag[gm.a0 + lane] = (ev >> lane) & 1ull ? 1 : 0;
-    if (!ev) return;
-    const int32_t *cg = k.ca.cand + s.c0;
-    uint64_t *rows = k.gmask + (int64_t)gm.a0 * k.nchT;
-    const int cnt = group_round<WRAP, true>(k.p64, cg, s, bx.L, gm, gm.h, ev, rows, k.nchT, ws);
-    ws.pairs += (unsigned long long)uni(wave_sum_i(cnt));
+    const double rx = uni_d(readlane_d(gm.rx, m)), ry = uni_d(readlane_d(gm.ry, m)),
+                 rz = uni_d(readlane_d(gm.rz, m));
+    const double hm = uni_d(readlane_d(gm.h, m));
+    const int i = uni(readlane_i(gm.i, m));
+    const double xm = WRAP ? to_frame(rx, s.cx, L) : rx;
+    const double ym = WRAP ? to_frame(ry, s.cy, L) : ry;
+    const double zm = WRAP ? to_frame(rz, s.cz, L) : rz;
+    HydroPairS<KER, ACC> hp;
+    hp.init(k, i, rx, ry, rz, L, hm, wrap);
+    hp.S = S;
+    hp.gc = gc;
+    GFifo<HEnt, GFB_H> q{fifo, 0, 0};
+    const int nch = (gc.nc + 63) >> 6;
+    const int RC = S.C >> 6;
+    int nn = 0;
+    for (int c = 0; c < nch; c++) {
+        const int slot = (c << 6) + lane;
+        uint64_t mk;
+        if (m < GMR && c < RC) {
+            mk = uni_u64(S.rows[m * RC + c]);
+        } else {
+            double x, y, z, hj;
+            int j;
+            cand_rec(S, gc, slot, x, y, z, hj, j);
+            const double fx = WRAP ? to_frame(x, s.cx, L) : x;
+            const double fy = WRAP ? to_frame(y, s.cy, L) : y;
+            const double fz = WRAP ? to_frame(z, s.cz, L) : z;
+            const double hh = fmax(hm, hj);
+            const double E = WRAP ? 0x1p-44 * (L * hh + hh * hh) : 0.0;
+            mk = ballot(in_ball<WRAP>(fx, fy, fz, xm, ym, zm, hh * hh, E,
+                                      [&]() { return r2_of(x, y, z, rx, ry, rz, L, true); }) &&
+                        j != i);
+        }
+        nn += popc64(mk);
+        q.push(mk, HEnt{slot}, hp);
+    }
+    q.flush(hp);
+    hydro_write<KER, ACC>(k, i, hp);
+    return nn;
 }
 } // namespace
 
@@ -2108,51 +2403,64 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
                         (float)sqrt(gamma * gm1 * uu), (float)hi);
 }
 
-// One wave per group (groups from per-XCD work queues): one filter round of
-// its members over the superset with r < max(h_i, h_j), j != i.  Members
-// that the superset does not cover are listed for k_hydro_solo.
-__global__ __launch_bounds__(64) void k_hgroup(HydroK k)
+// Hydro, one workgroup per group: the members the superset covers (all of
+// them, or in a reuse pass those whose spheres, grown by the drift, stay
+// inside the walked ball) take one filter round over the staged superset
+// together, then each is streamed by one wave into its force sums; the
+// others are listed for k_hydro_solo.
+template <int KER, typename ACC>
+__global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_hgrp(HydroK k)
 {
-    const int G = uni(*k.ga.n_groups);
-    Queue wq = queue_open(k.st->qctr2, G);
+    extern __shared__ __align__(16) char lds_raw[];
+    const GLds S = glds_carve(lds_raw, k.C, true);
+    const int lane = lane_id();
+    const int wv = uni((int)(threadIdx.x >> 6));
+    HEnt *fifo = (HEnt *)(S.fifo + (size_t)wv * 128 * GFB_H * sizeof(HEnt));
+    Queue wq = queue_open(k.st->qctr2, uni(*k.ga.n_groups));
     WaveStats ws;
     // reused supersets: the largest displacement and h growth since the walk
     const double dl = k.drift ? __longlong_as_double((long long)k.drift[0]) : 0.0;
     const double dh = k.drift ? __longlong_as_double((long long)k.drift[1]) : 0.0;
-    for (int g = queue_next(wq); g >= 0; g = queue_next(wq)) {
+    for (;;) {
+        const int g = wg_take(wq, S);
+        if (g < 0) break;
         const GSup s = load_gsup(k.ca.sup + g);
-        const BoxInfo bx = box_info(k.g, uni(k.ga.act[uni(k.ga.goff[g])]));
-        if ((s.flags & GSUP_WRAP) || k.drift)
-            hydro_filter<true>(k, g, s, bx, dl, dh, ws);
-        else
-            hydro_filter<false>(k, g, s, bx, dl, dh, ws);
+        const int a0 = uni(k.ga.goff[g]);
+        const int M = min(uni(k.ga.goff[g + 1]) - a0, 64);
+        const BoxInfo bx = box_info(k.g, uni(k.ga.act[a0]));
+        const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
+        const GCand gc{k.ca.cand + s.c0, s.nc, k.p64};
+        const GMem gm = grp_members(k.g, k.ga, k.active, a0, M, s, bx.L, 0.0);
+        const bool kept = !k.drift || (gm.h + gm.d + dl <= s.cov && gm.d + dl + dh <= s.rs);
+        const uint64_t livem = ballot(gm.live);
+        const uint64_t dm = (s.flags & GSUP_SOLO) ? livem : ballot(gm.live && !kept);
+        if (wv == 0) {
+            defer_members(dm, a0 + lane, k.dfr, k.st);
+            ws.deferred += (uint32_t)popc64(dm);
+        }
+        const uint64_t ev = livem & ~dm;
+        if (!(s.flags & GSUP_SOLO)) stage_cands<true>(S, gc, nullptr);
+        __syncthreads();
+        if (ev) {
+            if (wrap)
+                grp_round<true, true>(S, gc, s, bx.L, ev, gm, nullptr);
+            else
+                grp_round<false, true>(S, gc, s, bx.L, ev, gm, nullptr);
+            __syncthreads();
+        }
+        // the r-th member is streamed by wave r mod GW
+        uint64_t rest = ev;
+        for (int r = 0; rest; r++) {
+            const int m = ctz64(rest);
+            rest &= rest - 1ull;
+            if (r % GW != wv) continue;
+            const int c = wrap ? hydro_emit<KER, ACC, true>(k, S, gc, s, bx.L, wrap, gm, m, fifo)
+                               : hydro_emit<KER, ACC, false>(k, S, gc, s, bx.L, wrap, gm, m, fifo);
+            ws.pairs += (unsigned long long)c;
+            ws.tests += (unsigned long long)s.nc;
+        }
     }
     ws.flush(k.st);
-}
-
-// One wave per member filtered in its group: the force sums over the
-// neighbours its mask row holds.
-template <int KER, typename ACC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? 5 : 1))) void k_hsum(HydroK k)
-{
-    extern __shared__ __align__(16) char lds_raw[];
-    HEnt *fifo = (HEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
-    const int A = uni(*k.ga.n_act);
-    const ItemRange ar = item_range(A);
-    for (int a = ar.i; a < ar.end; a += ar.stride) {
-        if (!uni(k.gflag[a])) continue;
-        const int i = uni(k.ga.act[a]);
-        const GSup s = load_gsup(k.ca.sup + uni(k.ca.grp[a]));
-        const BoxInfo bx = box_info(k.g, i);
-        const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
-        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, i, uni_d(k.g.x[i]), uni_d(k.g.y[i]),
-                                                      uni_d(k.g.z[i]), bx.L, uni_d(k.g.h[i]), wrap);
-        FifoH q{fifo, 0};
-        int nn = 0;
-        stream_row<HydroPair<KER, ACC>, FifoH, HEnt>(k.ca.cand, s.c0, s.nc,
-                                                     k.gmask + (int64_t)a * k.nchT, q, hp, nn);
-        hydro_write<KER, ACC>(k, i, hp);
-    }
 }
 
 // The hydro members that their group's superset does not cover (their group
@@ -2445,14 +2753,23 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     const sfc_density_params &dp = a.dp;
     const int T = dp.t_cand;
     auto ks = k_dens_solo<KER, ACC>;
-    auto kb = k_dsum<KER, ACC>;
+    auto kg = k_dgrp<KER, ACC>;
     const size_t lds_s = MEM_WAVES * mem_lds_bytes(T, true);
-    const size_t lds_b = (size_t)MEM_WAVES * FIFO_BYTES;
     hipError_t e = allow_lds(ks, lds_s);
     if (e != hipSuccess) return e;
-    // the members that leave their group are few: one workgroup per CU
-    const unsigned grid_s = (unsigned)((sb.cu_count + 7) / 8 * 8);
-    const int64_t priv = (int64_t)grid_s * MEM_WAVES * T;
+    // the members that leave their group are few but walk the tree alone,
+    // latency bound: four workgroups per CU, each wave with a private slot
+    // when the slots fit in half the buffer (else one workgroup per CU with
+    // slots, else four without)
+    unsigned grid_s = (unsigned)((4 * sb.cu_count + 7) / 8 * 8);
+    int64_t priv = (int64_t)grid_s * MEM_WAVES * T;
+    if (priv > sb.cand_cap / 2) {
+        const unsigned g1 = (unsigned)((sb.cu_count + 7) / 8 * 8);
+        if ((int64_t)g1 * MEM_WAVES * T <= sb.cand_cap / 2) {
+            grid_s = g1;
+            priv = (int64_t)g1 * MEM_WAVES * T;
+        }
+    }
     SearchBufs gs = sb;
     if (priv <= sb.cand_cap / 2) gs.cand_cap = sb.cand_cap - priv;
     k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.h, p.m, sb.pos4,
@@ -2483,18 +2800,16 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.dn = dp.dn;
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
-    k.nchT = T / 64;
+    k.C = T < GC_MAX ? T : GC_MAX;
     k.drift = dp.reuse ? sb.drift : nullptr;
     k.active = dp.reuse ? p.active : nullptr;
     k.dfr = sb.dfr;
     k.dstate = sb.dstate;
-    k.gmask = sb.gmask;
-    k.gflag = sb.gflag;
-    if ((e = launch_persistent(k_dgroup, s, k, 64, 0, sb.cu_count, p.n)) != hipSuccess) return e;
+    if ((e = launch_persistent(kg, s, k, 64 * GW, glds_bytes(k.C, false), sb.cu_count, p.n * GW)) !=
+        hipSuccess)
+        return e;
     ks<<<grid_s, 64 * MEM_WAVES, lds_s, s>>>(k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_persistent(kb, s, k, 64 * MEM_WAVES, lds_b, sb.cu_count, p.n)) != hipSuccess)
-        return e;
     if (!dp.reuse) return hipSuccess;
     k_reuse_check<<<1, 64, 0, s>>>(sb.drift, st);
     return hipGetLastError();
@@ -2504,12 +2819,10 @@ template <int KER, typename ACC>
 hipError_t run_hydro(hipStream_t s, const HydroK &k, const SearchBufs &sb, int64_t n)
 {
     const size_t lds_s = (size_t)MEM_WAVES * HSOLO_WAVE_LDS;
-    const size_t lds_b = (size_t)MEM_WAVES * FIFO_BYTES;
-    hipError_t e = launch_persistent(k_hgroup, s, k, 64, 0, sb.cu_count, n);
+    hipError_t e = launch_persistent(k_hgrp<KER, ACC>, s, k, 64 * GW, glds_bytes(k.C, true),
+                                     sb.cu_count, n * GW);
     if (e == hipSuccess)
         e = launch_persistent(k_hydro_solo<KER, ACC>, s, k, 64 * MEM_WAVES, lds_s, sb.cu_count, n);
-    if (e == hipSuccess)
-        e = launch_persistent(k_hsum<KER, ACC>, s, k, 64 * MEM_WAVES, lds_b, sb.cu_count, n);
     return e;
 }
 } // namespace
@@ -2561,9 +2874,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
-    k.nchT = hp.t_cand / 64;
-    k.gmask = sb.gmask;
-    k.gflag = sb.gflag;
+    k.C = hp.t_cand < GC_MAX ? hp.t_cand : GC_MAX;
     k.drift = hp.reuse ? sb.drift : nullptr;
     k.active = hp.reuse ? p.active : nullptr;
     k.dfr = sb.dfr;

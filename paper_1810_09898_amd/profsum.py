@@ -10,8 +10,8 @@
         scaled by the reading of a plain copy of known size (calib.py) to give
         HBM bytes; TCC_HIT / TCC_MISS give the L2 hit rate.  A "call" is one
         library entry point: density = the record kernel, the walk, the group
-        kernel, the solo kernel and the sum kernel; hydro_force = the max-h
-        refit, the record kernel, the walk, the group, solo and sum kernels.  The source hash of the
+        kernel and the solo kernel; hydro_force = the max-h refit, the record
+        kernel, the walk, the group and solo kernels.  The source hash of the
         search kernels is stored so that the numbers are dropped once the
         kernels change.
 """
@@ -72,20 +72,20 @@ def _dispatches(rows):
     return out
 
 
-DENS_CALL = ("k_dens_prep", "k_reset_pass", "k_walk", "k_dgroup", "k_dens_solo")
+DENS_CALL = ("k_dens_prep", "k_reset_pass", "k_walk", "k_dgrp")
 HYDRO_CALL = ("k_tree_leaves", "k_tree_up3", "k_tree_nchild", "k_hydro_prep", "k_reset_pass",
-              "k_walk", "k_hgroup", "k_hydro_solo")
+              "k_walk", "k_hgrp")
 
 
 def _calls(disp):
     """split the dispatch sequence into density and hydro_force calls: each
-    call ends with its per-member sum kernel; the kernels before it back to
+    call ends with its solo-member kernel; the kernels before it back to
     the call's first one belong to it"""
     items = list(disp.items())
     calls = {"density": [], "hydro_force": []}
     for k, (_, (name, _cs)) in enumerate(items):
-        for last, before, call in (("k_dsum", DENS_CALL, "density"),
-                                   ("k_hsum", HYDRO_CALL, "hydro_force")):
+        for last, before, call in (("k_dens_solo", DENS_CALL, "density"),
+                                   ("k_hydro_solo", HYDRO_CALL, "hydro_force")):
             if name != last:
                 continue
             seg = [items[k]]
