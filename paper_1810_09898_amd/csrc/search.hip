@@ -101,6 +101,14 @@ template <int KER, typename T> __device__ __forceinline__ void kern_eval_u(T q, 
     }
 }
 
+// w'(q) alone from q and u = 1 - q (the force terms need no w)
+template <int KER, typename T> __device__ __forceinline__ T kern_deval_u(T q, T u)
+{
+    if (KER == 0) return q < T(0.5) ? q * mad(T(18), q, T(-12)) : T(-6) * u * u;
+    const T u2 = u * u, u4 = u2 * u2, u7 = u4 * u2 * u;
+    return T(-22) * q * u7 * mad(q, mad(T(16), q, T(7)), T(1));
+}
+
 // 1 - q for q = sqrt(r2) / h, from the FP64 r2 and h2 = h^2: the difference
 // h2 - r2 is exact near the edge (the two are within a factor 2), so the
 // result has a small relative error even where it is tiny; 0 outside
@@ -316,10 +324,11 @@ struct Pos {
 // sizes gives each leaf its first flattened position; in a batch of 64
 // positions only a few leaves start, so each lane finds its leaf by walking
 // the (uniform) list of those starts, and reads the leaf's first particle
-// from the leaf's lane.  Two batches per step: their loads (visit.fetch)
-// overlap before visit.take consumes them in order.
+// from the leaf's lane.  V::EB batches per step: their loads (visit.fetch)
+// are in flight together before visit.take consumes them in order.
 template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4 inf, V &visit)
 {
+    constexpr int EB = V::EB;
     const int lane = lane_id();
     const bool isl = (vl >> lane) & 1ull;
     const int c = isl ? inf.y : 0;
@@ -332,11 +341,10 @@ template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4
     const int total = uni(readlane_i(incl, 63));
     const int pre = incl - c; // first flattened position of this lane's leaf
     int carry = 0;            // lane of the leaf covering the position before the batch
-    for (int t0 = 0; t0 < total; t0 += 128) {
-        const bool two = t0 + 64 < total;
-        int j[2];
+    for (int t0 = 0; t0 < total; t0 += 64 * EB) {
+        int j[EB];
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
+        for (int u = 0; u < EB; u++) {
             const int b0 = t0 + 64 * u;
             int own = carry;
             uint64_t st = ballot(isl && c > 0 && pre >= b0 && pre < b0 + 64);
@@ -352,11 +360,13 @@ template <class V> __device__ __forceinline__ void emit_leaves(uint64_t vl, int4
             const int p0 = __shfl(pre, own, 64);
             j[u] = f + (qc - p0);
         }
-        const auto p0 = visit.fetch(j[0]);
-        auto p1 = p0;
-        if (two) p1 = visit.fetch(j[1]);
-        visit.take(j[0], t0 + lane < total, p0);
-        if (two) visit.take(j[1], t0 + 64 + lane < total, p1);
+        decltype(visit.fetch(0)) p[EB];
+#pragma unroll
+        for (int u = 0; u < EB; u++)
+            if (u == 0 || t0 + 64 * u < total) p[u] = visit.fetch(j[u]);
+#pragma unroll
+        for (int u = 0; u < EB; u++)
+            if (u == 0 || t0 + 64 * u < total) visit.take(j[u], t0 + 64 * u + lane < total, p[u]);
     }
 }
 
@@ -639,6 +649,7 @@ __device__ __forceinline__ int64_t cand_alloc(DevStatus *st, int64_t cap, int x,
 }
 
 struct AppendCand {
+    static constexpr int EB = 3; // leaf batches in flight (emit_leaves)
     const float4 *p4; // x, y, z and, for hydro, h in FP32
     int *cand;
     int T;            // most candidates a superset may hold
@@ -1202,6 +1213,7 @@ __device__ __forceinline__ void stream_masks(const int32_t *cand, int64_t c0, in
 
 // counts |{j : r2 < h2}| over walked particles (solo path)
 struct CountVisit {
+    static constexpr int EB = 2; // leaf batches in flight (emit_leaves)
     const double *x, *y, *z;
     double xi, yi, zi, L, h2;
     int cnt;
@@ -1225,6 +1237,7 @@ struct CountVisit {
 
 // filter walked particles against one particle and push the neighbours
 template <int MODE, class F, class Q = Fifo> struct StreamVisit {
+    static constexpr int EB = 2; // leaf batches in flight (emit_leaves)
     const double *x, *y, *z, *h;
     double xi, yi, zi, L, hi;
     int i;
@@ -1268,11 +1281,11 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
 // around h^2 (the two evaluations differ by less than 2^-48 L h + 2^-50 h^2),
 // and on the canonical r^2 of the raw coordinates inside it.
 constexpr int GW = 4;               // waves per group workgroup
-constexpr int GKB = 2;              // candidate chunks a wave holds during a round
+constexpr int GKB = 4;              // candidate chunks a wave holds during a round
 constexpr int GSTG = 4;             // candidates a thread stages per pass
 constexpr int GC_MAX = 1024;        // staged candidates at most
 constexpr int GMR = 32;             // members whose masks over the staged chunks are kept
-constexpr int GFB_D = 1, GFB_H = 2; // batches a group wave's FIFO hands over at once (density, hydro)
+constexpr int GFB = 1;              // batches a group wave's FIFO hands over at once
 
 // shift of a coordinate into the frame of the centre c: x - L when it lies
 // more than L/2 above c, x + L when more than L/2 below
@@ -1302,40 +1315,44 @@ __device__ __forceinline__ void defer_members(uint64_t dm, int a, int32_t *dfr, 
 
 // LDS of a group workgroup
 struct GLds {
-    double *cx, *cy, *cz; // [C] density: staged candidates' raw FP64 positions (NaN past the superset)
+    double *cx, *cy, *cz; // [C] staged candidates: raw FP64 positions (NaN past the superset)
     uint64_t *rows;       // [GMR][C / 64]: the masks of member m over the staged chunks
-    float *cm;            // [C] density: m_j
-    int32_t *cj;          // [C] hydro: staged candidates' particle index (-1 past the superset)
-    int32_t *mcnt;        // [3][64] density: neighbour counts of member m, round r in r % 3
+    double *mh;           // [64] h of member m in the current round
+    double *fin;          // [2][64] the lane-reduced sums of member m (W, its h derivative)
+    uint64_t *ctl64;      // [2]: members iterating in the next round, members done
+    float *cm;            // [C] staged candidates: m_j
+    int32_t *mcnt;        // [64] neighbour counts of member m in the round
     int32_t *ctl;         // [8]: the group taken
     char *fifo;           // GW FIFOs of 128 * (batches at once) entries
     int C;
 };
-__host__ __device__ constexpr size_t glds_bytes(int C, bool hydro)
+__host__ __device__ constexpr size_t glds_bytes(int C)
 {
-    return (size_t)C * (hydro ? 4 : 28) + (size_t)8 * GMR * (C / 64) + 3 * 64 * 4 + 8 * 4 +
-           (size_t)GW * 128 * (hydro ? GFB_H : GFB_D) * 4;
+    return (size_t)C * 28 + (size_t)8 * GMR * (C / 64) + 8 * 64 * 3 + 8 * 2 + 64 * 4 + 8 * 4 +
+           (size_t)GW * 128 * GFB * 4;
 }
-__device__ __forceinline__ GLds glds_carve(char *p, int C, bool hydro)
+__device__ __forceinline__ GLds glds_carve(char *p, int C)
 {
     GLds S;
     S.C = C;
-    S.cx = S.cy = S.cz = nullptr;
-    if (!hydro) {
-        S.cx = (double *)p;
-        p += 8 * (size_t)C;
-        S.cy = (double *)p;
-        p += 8 * (size_t)C;
-        S.cz = (double *)p;
-        p += 8 * (size_t)C;
-    }
+    S.cx = (double *)p;
+    p += 8 * (size_t)C;
+    S.cy = (double *)p;
+    p += 8 * (size_t)C;
+    S.cz = (double *)p;
+    p += 8 * (size_t)C;
     S.rows = (uint64_t *)p;
     p += (size_t)8 * GMR * (C / 64);
-    S.cm = hydro ? nullptr : (float *)p;
-    S.cj = hydro ? (int32_t *)p : nullptr;
+    S.mh = (double *)p;
+    p += 8 * 64;
+    S.fin = (double *)p;
+    p += 8 * 128;
+    S.ctl64 = (uint64_t *)p;
+    p += 8 * 2;
+    S.cm = (float *)p;
     p += 4 * (size_t)C;
     S.mcnt = (int32_t *)p;
-    p += 3 * 64 * 4;
+    p += 64 * 4;
     S.ctl = (int32_t *)p;
     p += 4 * 8;
     S.fifo = p;
@@ -1350,21 +1367,14 @@ struct GCand {
 };
 
 // Stage the first min(nc, C) candidates (all threads of the workgroup):
-// density their positions and masses, hydro their particle indices (hydro
-// reads each candidate's record once in its single filter round, so only
-// the index is kept).  The slots past nc up to the end of its chunk get NaN
-// positions (index -1), on which every test fails.  Each pass loads GSTG
+// their positions and masses.  The slots past nc up to the end of its chunk
+// get NaN positions, on which every test fails.  Each pass loads GSTG
 // indices per thread, then their records.
-template <bool HYDRO>
 __device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc, const float *__restrict__ m)
 {
     const int n = min(gc.nc, S.C);
     const int npad = min((gc.nc + 63) & ~63, S.C);
     const double nan = __builtin_nan("");
-    if (HYDRO) {
-        for (int t = (int)threadIdx.x; t < npad; t += GW * 64) S.cj[t] = t < n ? gc.cg[t] : -1;
-        return;
-    }
     for (int base = 0; base < npad; base += GSTG * GW * 64) {
         int j[GSTG];
 #pragma unroll
@@ -1431,27 +1441,6 @@ __device__ __forceinline__ bool in_ball(double fx, double fy, double fz, double 
         if (amb) hit = raw_r2() < lim;
     }
     return hit;
-}
-
-// hydro candidate `slot`: its particle index (staged, or from global memory
-// past the staged part) and its FP64 record; NaN position and index -1 past
-// the superset
-__device__ __forceinline__ int cand_j(const GLds &S, const GCand &gc, int slot)
-{
-    int j = S.cj[min(slot, S.C - 1)];
-    if (slot >= S.C) j = slot < gc.nc ? gc.cg[slot] : -1;
-    return j;
-}
-__device__ __forceinline__ void cand_rec(const GLds &S, const GCand &gc, int slot, double &x, double &y,
-                                         double &z, double &hj, int &j)
-{
-    j = cand_j(S, gc, slot);
-    const double4 p = gc.p64[j < 0 ? 0 : j];
-    const double nan = __builtin_nan("");
-    x = j < 0 ? nan : p.x;
-    y = j < 0 ? nan : p.y;
-    z = j < 0 ? nan : p.z;
-    hj = j < 0 ? 0.0 : p.w;
 }
 
 // FIFO of a group workgroup's wave: a ring of 128 B entries in LDS; the k-th
@@ -1533,11 +1522,10 @@ __device__ __forceinline__ GMem grp_members(const Geom &geo, const GroupArg &ga,
 
 // One filter round (all waves of the workgroup) of the members in `ev`: wave
 // w takes blocks w, w + GW, ... of GKB chunks, holds their candidates in
-// registers and tests them against every member of ev (member data from
-// lane m by readlane).  Member m's mask over staged chunk c goes to
-// S.rows[m * (C / 64) + c] (m < GMR); density adds the counts to cnt[m].
-// Density: r < h_m; hydro: r < max(h_m, h_j) and j != i_m.
-template <bool WRAP, bool HYDRO>
+// registers and tests them against every member of ev (r < h_m; member data
+// from lane m by readlane).  Member m's mask over staged chunk c goes to
+// S.rows[m * (C / 64) + c] (m < GMR); the counts are added to cnt_m[m].
+template <bool WRAP>
 __device__ __forceinline__ void grp_round(const GLds &S, const GCand &gc, const GSup &s, double L,
                                           uint64_t ev, const GMem &gm, int32_t *cnt_m)
 {
@@ -1549,19 +1537,14 @@ __device__ __forceinline__ void grp_round(const GLds &S, const GCand &gc, const 
     const double ym = WRAP ? to_frame(gm.ry, s.cy, L) : gm.ry;
     const double zm = WRAP ? to_frame(gm.rz, s.cz, L) : gm.rz;
     const double limv = gm.h * gm.h;
-    const double Ev = (WRAP && !HYDRO) ? 0x1p-44 * (L * gm.h + gm.h * gm.h) : 0.0;
+    const double Ev = WRAP ? 0x1p-44 * (L * gm.h + gm.h * gm.h) : 0.0;
     int cntv = 0;
     for (int cb = wv * GKB; cb < nch; cb += GW * GKB) {
-        double x[GKB], y[GKB], z[GKB], hj[GKB];
-        int jj[GKB];
+        double x[GKB], y[GKB], z[GKB];
 #pragma unroll
         for (int u = 0; u < GKB; u++) {
             if (cb + u < nch) {
-                const int slot = ((cb + u) << 6) + lane;
-                if (HYDRO)
-                    cand_rec(S, gc, slot, x[u], y[u], z[u], hj[u], jj[u]);
-                else
-                    cand_xyz(S, gc, slot, x[u], y[u], z[u]);
+                cand_xyz(S, gc, ((cb + u) << 6) + lane, x[u], y[u], z[u]);
                 if (WRAP) {
                     x[u] = to_frame(x[u], s.cx, L);
                     y[u] = to_frame(y[u], s.cy, L);
@@ -1574,43 +1557,28 @@ __device__ __forceinline__ void grp_round(const GLds &S, const GCand &gc, const 
             const int m = ctz64(rest);
             rest &= rest - 1ull;
             const double xmm = readlane_d(xm, m), ymm = readlane_d(ym, m), zmm = readlane_d(zm, m);
-            const double lim = HYDRO ? 0.0 : readlane_d(limv, m);
-            const double E = (WRAP && !HYDRO) ? readlane_d(Ev, m) : 0.0;
-            const double hmm = HYDRO ? readlane_d(gm.h, m) : 0.0;
-            const int imm = HYDRO ? readlane_i(gm.i, m) : 0;
+            const double lim = readlane_d(limv, m);
+            const double E = WRAP ? readlane_d(Ev, m) : 0.0;
             int cnt = 0;
 #pragma unroll
             for (int u = 0; u < GKB; u++) {
                 if (cb + u < nch) {
                     const int slot = ((cb + u) << 6) + lane;
-                    auto raw = [&]() {
-                        double px, py, pz, ph;
-                        int pj;
-                        if (HYDRO)
-                            cand_rec(S, gc, slot, px, py, pz, ph, pj);
-                        else
-                            cand_xyz(S, gc, slot, px, py, pz);
+                    const bool hit = in_ball<WRAP>(x[u], y[u], z[u], xmm, ymm, zmm, lim, E, [&]() {
+                        double px, py, pz;
+                        cand_xyz(S, gc, slot, px, py, pz);
                         return r2_of(px, py, pz, readlane_d(gm.rx, m), readlane_d(gm.ry, m),
                                      readlane_d(gm.rz, m), L, true);
-                    };
-                    bool hit;
-                    if (HYDRO) {
-                        const double hh = fmax(hmm, hj[u]);
-                        const double Eu = WRAP ? 0x1p-44 * (L * hh + hh * hh) : 0.0;
-                        hit = in_ball<WRAP>(x[u], y[u], z[u], xmm, ymm, zmm, hh * hh, Eu, raw) &&
-                              jj[u] != imm;
-                    } else {
-                        hit = in_ball<WRAP>(x[u], y[u], z[u], xmm, ymm, zmm, lim, E, raw);
-                    }
+                    });
                     const uint64_t mk = ballot(hit);
-                    if (!HYDRO) cnt += popc64(mk);
+                    cnt += popc64(mk);
                     if (m < GMR && cb + u < RC && lane == 0) S.rows[m * RC + cb + u] = mk;
                 }
             }
-            if (!HYDRO) cntv += lane == m ? cnt : 0;
+            cntv += lane == m ? cnt : 0;
         }
     }
-    if (!HYDRO && ((ev >> lane) & 1ull)) atomicAdd(&cnt_m[lane], cntv);
+    if ((ev >> lane) & 1ull) atomicAdd(&cnt_m[lane], cntv);
 }
 
 // the group taken by the workgroup (wave 0 takes it; -1: none left)
@@ -1735,13 +1703,11 @@ __device__ __forceinline__ DensPair<KER, ACC> dens_pair(const DensK &k, double x
     return pp;
 }
 
-// the sums of particle i at its final h: rho, drho/dh, f
-template <int KER, typename ACC, class P>
-__device__ void dens_write_sums(const DensK &k, int i, double h, const P &pp)
+// rho, drho/dh and f of particle i at its final h from its lane-reduced sums
+// of m_j w and m_j (q w' + 3 w) (any lane)
+template <int KER>
+__device__ void dens_finish(const DensK &k, int i, double h, double Sw, double Sd)
 {
-    double Sw = (double)wave_sum_f_or_d(pp.sw.value());
-    double Sd = (double)wave_sum_f_or_d(pp.sd.value());
-    if (lane_id() != 0) return;
     constexpr double C = knorm<KER>();
     double h3 = h * h * h;
     double rho = C * Sw / h3;
@@ -1825,7 +1791,9 @@ __device__ __forceinline__ int iterate(const DensK &k, const Member &M, const Me
     bool first = true;
     while (it < k.max_iter) {
         if (!(h + M.d <= M.s.cov)) return 0;
-        nn = count_pass(k.g, k.pos4, k.ca.cand, M, h, true, S, first);
+        // own supersets carry GSUP_WRAP; a reused one may fold after the drift
+        const bool wrap = (M.s.flags & GSUP_WRAP) || k.drift;
+        nn = count_pass(k.g, k.pos4, k.ca.cand, M, h, wrap, S, first);
         ws.tests += (unsigned)M.s.nc;
         first = false;
         it++;
@@ -1892,15 +1860,17 @@ __device__ __forceinline__ int dens_emit(const DensK &k, const GLds &S, const GC
     pp.S = S;
     pp.gc = gc;
     pp.m = k.m;
-    GFifo<DEnt, GFB_D> q{fifo, 0, 0};
+    GFifo<DEnt, GFB> q{fifo, 0, 0};
     const int nch = (gc.nc + 63) >> 6;
     const int RC = S.C >> 6;
+    // the member's masks over the staged chunks, word c in lane c
+    const uint64_t row = (m < GMR && lane < RC) ? S.rows[m * RC + lane] : 0ull;
     int nn = 0;
     for (int c = 0; c < nch; c++) {
         const int slot = (c << 6) + lane;
         uint64_t mk;
         if (m < GMR && c < RC) {
-            mk = uni_u64(S.rows[m * RC + c]);
+            mk = uni_u64(readlane_u64(row, c));
         } else {
             double x, y, z;
             cand_xyz(S, gc, slot, x, y, z);
@@ -1914,28 +1884,35 @@ __device__ __forceinline__ int dens_emit(const DensK &k, const GLds &S, const GC
         q.push(mk, DEnt{slot}, pp);
     }
     q.flush(pp);
-    dens_write_sums<KER, ACC>(k, uni(readlane_i(gm.i, m)), h, pp);
+    // the lanes' sums, reduced by the fixed butterfly, for the workgroup's
+    // lane-parallel finish
+    const double Sw = (double)wave_sum_f_or_d(pp.sw.value());
+    const double Sd = (double)wave_sum_f_or_d(pp.sd.value());
+    if (lane == 0) {
+        S.fin[m] = Sw;
+        S.fin[64 + m] = Sd;
+    }
     return nn;
 }
 } // namespace
 
 // Density, one workgroup per group: the members iterate h together on the
-// staged superset, one filter round at a time.  Every wave keeps the
-// members' h loop state in its lanes and applies the same h step after each
-// round (the round's counts are read from LDS after the one barrier of the
-// round; counts of round r go to buffer r % 3, so a buffer is cleared two
-// rounds after it was read).  Members whose h outgrows the superset, or
-// whose group kept none, are listed for k_dens_solo with the state they
-// reached; every member that finished is then streamed by one wave into its
-// sums from its masks of the last round.
+// staged superset, one filter round at a time.  Wave 0 keeps the members'
+// h loop state in its lanes: after the round's barrier it reads the counts,
+// applies the h step and publishes the new h and the next round's members
+// (a second barrier).  Members whose h outgrows the superset, or whose
+// group kept none, are listed for k_dens_solo with the state they reached;
+// every member that finished is then streamed by one wave into its sums from
+// its masks of the last round, and wave 0 finishes rho, drho/dh and f of
+// all of them, one lane each.
 template <int KER, typename ACC>
 __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_dgrp(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const GLds S = glds_carve(lds_raw, k.C, false);
+    const GLds S = glds_carve(lds_raw, k.C);
     const int lane = lane_id();
     const int wv = uni((int)(threadIdx.x >> 6));
-    DEnt *fifo = (DEnt *)(S.fifo + (size_t)wv * 128 * GFB_D * sizeof(DEnt));
+    DEnt *fifo = (DEnt *)(S.fifo + (size_t)wv * 128 * GFB * sizeof(DEnt));
     Queue wq = queue_open(k.st->qctr2, uni(*k.ga.n_groups));
     WaveStats ws;
     // a reused superset: every particle may have moved by dl since the walk
@@ -1950,47 +1927,54 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
         const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
         const GCand gc{k.ca.cand + s.c0, s.nc, k.p64};
         GMem gm = grp_members(k.g, k.ga, k.active, a0, M, s, bx.L, dl);
+        // wave 0: the h loop state of member `lane`
         int it = 0, nn = 0;
         int stt = gm.live ? ((s.flags & GSUP_SOLO) ? ST_DEFER : ST_ITER) : ST_DONE;
         if (stt == ST_ITER && !(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
         double lo = 0.0, hi = INFINITY;
         bool conv = false;
+        uint64_t ev = ballot(stt == ST_ITER); // the same in every wave at the start
         if (wv == 0) {
             S.mcnt[lane] = 0;
-            S.mcnt[64 + lane] = 0;
+            S.mh[lane] = gm.h;
         }
-        if (!(s.flags & GSUP_SOLO)) stage_cands<false>(S, gc, k.m);
+        if (!(s.flags & GSUP_SOLO)) stage_cands(S, gc, k.m);
         __syncthreads();
-        for (int round = 0; round <= k.max_iter; round++) {
-            const uint64_t ev = ballot(stt == ST_ITER);
-            if (!ev) break;
-            int32_t *cnt = S.mcnt + 64 * (round % 3);
-            if (wv == 0) S.mcnt[64 * ((round + 1) % 3) + lane] = 0;
+        for (int round = 0; ev && round <= k.max_iter; round++) {
             if (wrap)
-                grp_round<true, false>(S, gc, s, bx.L, ev, gm, cnt);
+                grp_round<true>(S, gc, s, bx.L, ev, gm, S.mcnt);
             else
-                grp_round<false, false>(S, gc, s, bx.L, ev, gm, cnt);
+                grp_round<false>(S, gc, s, bx.L, ev, gm, S.mcnt);
             __syncthreads();
-            if (wv == 0) ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)s.nc;
-            if ((ev >> lane) & 1ull) {
-                it++;
-                nn = cnt[lane];
-                if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
-                    conv = true;
-                    stt = ST_DONE;
-                } else if (it >= k.max_iter) {
-                    stt = ST_DONE;
-                } else {
-                    gm.h = h_step(nn, k.n_ngb, k.dn, gm.h, lo, hi);
-                    if (!(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
+            if (wv == 0) {
+                ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)s.nc;
+                if ((ev >> lane) & 1ull) {
+                    it++;
+                    nn = S.mcnt[lane];
+                    S.mcnt[lane] = 0;
+                    if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
+                        conv = true;
+                        stt = ST_DONE;
+                    } else if (it >= k.max_iter) {
+                        stt = ST_DONE;
+                    } else {
+                        gm.h = h_step(nn, k.n_ngb, k.dn, gm.h, lo, hi);
+                        S.mh[lane] = gm.h;
+                        if (!(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
+                    }
                 }
+                const uint64_t nx = ballot(stt == ST_ITER);
+                if (lane == 0) S.ctl64[0] = nx;
             }
+            __syncthreads();
+            ev = uni_u64(S.ctl64[0]);
+            if (wv != 0) gm.h = S.mh[lane];
         }
-        const bool done = gm.live && stt == ST_DONE;
         if (wv == 0) {
             // a member still iterating here has hit the round limit: impossible
             // while every round advances it, kept as a guard
             if (ballot(stt == ST_ITER)) guard_hit(k.st);
+            const bool done = gm.live && stt == ST_DONE;
             const uint64_t dm = ballot(gm.live && stt == ST_DEFER);
             if ((dm >> lane) & 1ull) k.dstate[a0 + lane] = make_double4(gm.h, lo, hi, (double)it);
             defer_members(dm, a0 + lane, k.dfr, k.st);
@@ -2003,9 +1987,13 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
             }
             ws.iters += (uint32_t)uni(wave_sum_i(done ? it : 0));
             ws.not_conv += (uint32_t)popc64(ballot(done && !conv));
+            const uint64_t dn = ballot(done);
+            if (lane == 0) S.ctl64[1] = dn;
         }
+        __syncthreads();
         // the r-th member that finished is streamed by wave r mod GW
-        uint64_t rest = ballot(done);
+        const uint64_t dn = uni_u64(S.ctl64[1]);
+        uint64_t rest = dn;
         for (int r = 0; rest; r++) {
             const int m = ctz64(rest);
             rest &= rest - 1ull;
@@ -2014,6 +2002,8 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
                                : dens_emit<KER, ACC, false>(k, S, gc, s, bx.L, wrap, gm, m, fifo);
             ws.pairs += (unsigned long long)c;
         }
+        __syncthreads();
+        if (wv == 0 && ((dn >> lane) & 1ull)) dens_finish<KER>(k, gm.i, gm.h, S.fin[lane], S.fin[64 + lane]);
     }
     ws.flush(k.st);
 }
@@ -2074,7 +2064,6 @@ struct HydroK {
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
-    int C; // candidates a group workgroup stages in LDS
 };
 
 namespace {
@@ -2128,12 +2117,11 @@ template <int KER, typename ACC> struct HydroAcc {
         }
         ACC r = acc_sqrt((ACC)r2d);
         ACC rinv = r > ACC(0) ? acc_rcp(r) : ACC(0);
-        ACC w, dwi, dwj;
         const ACC qi = r * hinv;
-        kern_eval_u<KER, ACC>(qi, tail_u<ACC>(h2, r2d, hinv * hinv, qi), w, dwi);
+        const ACC dwi = kern_deval_u<KER, ACC>(qi, tail_u<ACC>(h2, r2d, hinv * hinv, qi));
         ACC hjinv = acc_rcp(hj);
         const ACC qj = r * hjinv;
-        kern_eval_u<KER, ACC>(qj, tail_u<ACC>(pj.w * pj.w, r2d, hjinv * hjinv, qj), w, dwj);
+        const ACC dwj = kern_deval_u<KER, ACC>(qj, tail_u<ACC>(pj.w * pj.w, r2d, hjinv * hjinv, qj));
         ACC hj2 = hjinv * hjinv;
         ACC dWi = C * dwi * hinv4;
         ACC dWj = C * dwj * (hj2 * hj2);
@@ -2195,17 +2183,6 @@ template <int KER, typename ACC> struct HydroPair : HydroAcc<KER, ACC> {
     }
 };
 
-// neighbours given by their slot in a staged group superset
-template <int KER, typename ACC> struct HydroPairS : HydroAcc<KER, ACC> {
-    using Term = typename HydroAcc<KER, ACC>::Term;
-    GLds S;
-    GCand gc;
-    __device__ __forceinline__ Term term(const HEnt &e) const
-    {
-        const int j = cand_j(S, gc, e.j);
-        return this->make(j, gc.p64[j]);
-    }
-};
 
 template <int KER, typename ACC>
 __device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, int i, double xi, double yi,
@@ -2241,55 +2218,6 @@ __device__ void hydro_write(const HydroK &k, int i, const P &hp)
     if (k.out.dudt64) k.out.dudt64[i] = du;
 }
 
-// Member m's hydro neighbours (one wave): its masks of the filter round
-// (re-tested for members past GMR and chunks past the staged ones) pushed
-// in candidate order through the wave's FIFO into the force sums.  Returns
-// the neighbour count.
-template <int KER, typename ACC, bool WRAP>
-__device__ __forceinline__ int hydro_emit(const HydroK &k, const GLds &S, const GCand &gc, const GSup &s,
-                                          double L, bool wrap, const GMem &gm, int m, HEnt *fifo)
-{
-    const int lane = lane_id();
-    const double rx = uni_d(readlane_d(gm.rx, m)), ry = uni_d(readlane_d(gm.ry, m)),
-                 rz = uni_d(readlane_d(gm.rz, m));
-    const double hm = uni_d(readlane_d(gm.h, m));
-    const int i = uni(readlane_i(gm.i, m));
-    const double xm = WRAP ? to_frame(rx, s.cx, L) : rx;
-    const double ym = WRAP ? to_frame(ry, s.cy, L) : ry;
-    const double zm = WRAP ? to_frame(rz, s.cz, L) : rz;
-    HydroPairS<KER, ACC> hp;
-    hp.init(k, i, rx, ry, rz, L, hm, wrap);
-    hp.S = S;
-    hp.gc = gc;
-    GFifo<HEnt, GFB_H> q{fifo, 0, 0};
-    const int nch = (gc.nc + 63) >> 6;
-    const int RC = S.C >> 6;
-    int nn = 0;
-    for (int c = 0; c < nch; c++) {
-        const int slot = (c << 6) + lane;
-        uint64_t mk;
-        if (m < GMR && c < RC) {
-            mk = uni_u64(S.rows[m * RC + c]);
-        } else {
-            double x, y, z, hj;
-            int j;
-            cand_rec(S, gc, slot, x, y, z, hj, j);
-            const double fx = WRAP ? to_frame(x, s.cx, L) : x;
-            const double fy = WRAP ? to_frame(y, s.cy, L) : y;
-            const double fz = WRAP ? to_frame(z, s.cz, L) : z;
-            const double hh = fmax(hm, hj);
-            const double E = WRAP ? 0x1p-44 * (L * hh + hh * hh) : 0.0;
-            mk = ballot(in_ball<WRAP>(fx, fy, fz, xm, ym, zm, hh * hh, E,
-                                      [&]() { return r2_of(x, y, z, rx, ry, rz, L, true); }) &&
-                        j != i);
-        }
-        nn += popc64(mk);
-        q.push(mk, HEnt{slot}, hp);
-    }
-    q.flush(hp);
-    hydro_write<KER, ACC>(k, i, hp);
-    return nn;
-}
 } // namespace
 
 __global__ void k_dens_prep(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
@@ -2403,62 +2331,85 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
                         (float)sqrt(gamma * gm1 * uu), (float)hi);
 }
 
-// Hydro, one workgroup per group: the members the superset covers (all of
-// them, or in a reuse pass those whose spheres, grown by the drift, stay
-// inside the walked ball) take one filter round over the staged superset
-// together, then each is streamed by one wave into its force sums; the
-// others are listed for k_hydro_solo.
+
+// Hydro, one wave per active particle: the group superset filtered to
+// r < max(h_i, h_j), j != i, decided on the FP32 positions and h wherever
+// that is safely away from the edge and by the FP64 test inside the band,
+// the pairs streamed through the FIFO into the force sums.  Members the
+// superset does not cover are listed for k_hydro_solo.
 template <int KER, typename ACC>
-__global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_hgrp(HydroK k)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? 5 : 1))) void k_hmem(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
-    const GLds S = glds_carve(lds_raw, k.C, true);
+    HEnt *fifo = (HEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
     const int lane = lane_id();
-    const int wv = uni((int)(threadIdx.x >> 6));
-    HEnt *fifo = (HEnt *)(S.fifo + (size_t)wv * 128 * GFB_H * sizeof(HEnt));
-    Queue wq = queue_open(k.st->qctr2, uni(*k.ga.n_groups));
+    const int A = uni(*k.ga.n_act);
+    const ItemRange ar = item_range(A);
     WaveStats ws;
     // reused supersets: the largest displacement and h growth since the walk
     const double dl = k.drift ? __longlong_as_double((long long)k.drift[0]) : 0.0;
     const double dh = k.drift ? __longlong_as_double((long long)k.drift[1]) : 0.0;
-    for (;;) {
-        const int g = wg_take(wq, S);
-        if (g < 0) break;
-        const GSup s = load_gsup(k.ca.sup + g);
-        const int a0 = uni(k.ga.goff[g]);
-        const int M = min(uni(k.ga.goff[g + 1]) - a0, 64);
-        const BoxInfo bx = box_info(k.g, uni(k.ga.act[a0]));
-        const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
-        const GCand gc{k.ca.cand + s.c0, s.nc, k.p64};
-        const GMem gm = grp_members(k.g, k.ga, k.active, a0, M, s, bx.L, 0.0);
-        const bool kept = !k.drift || (gm.h + gm.d + dl <= s.cov && gm.d + dl + dh <= s.rs);
-        const uint64_t livem = ballot(gm.live);
-        const uint64_t dm = (s.flags & GSUP_SOLO) ? livem : ballot(gm.live && !kept);
-        if (wv == 0) {
-            defer_members(dm, a0 + lane, k.dfr, k.st);
-            ws.deferred += (uint32_t)popc64(dm);
+    for (int a = ar.i; a < ar.end; a += ar.stride) {
+        const Member M = member(k.g, k.ga, k.ca, a);
+        if (k.active && !uni(k.active[M.i])) continue; // reuse: the members active now
+        const bool kept = !k.drift || (M.h + M.d + dl <= M.s.cov && M.d + dl + dh <= M.s.rs);
+        if ((M.s.flags & GSUP_SOLO) || !kept) {
+            ws.deferred++;
+            if (lane == 0) k.dfr[atomicAdd(&k.st->n_dfr, 1ull)] = a;
+            continue;
         }
-        const uint64_t ev = livem & ~dm;
-        if (!(s.flags & GSUP_SOLO)) stage_cands<true>(S, gc, nullptr);
-        __syncthreads();
-        if (ev) {
-            if (wrap)
-                grp_round<true, true>(S, gc, s, bx.L, ev, gm, nullptr);
-            else
-                grp_round<false, true>(S, gc, s, bx.L, ev, gm, nullptr);
-            __syncthreads();
+        const bool wrap = (M.s.flags & GSUP_WRAP) || k.drift;
+        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M.i, M.xi, M.yi, M.zi, M.bx.L, M.h, wrap);
+        FifoH q{fifo, 0};
+        // the FP32 screen: coordinates off by at most 2^-24 L each, h by
+        // 2^-24 h; near r = max(h_i, h_j) the FP32 r^2 is within
+        // 2^-19 (L hm + hm^2) of the FP64 one
+        const float xf = (float)M.xi, yf = (float)M.yi, zf = (float)M.zi, Lf = (float)M.bx.L,
+                    hf = (float)M.h;
+        const int nc = M.s.nc;
+        const int nch = (nc + 63) >> 6;
+        const int32_t *cg = k.ca.cand + M.s.c0;
+        ws.tests += (unsigned)nc;
+        int jn[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) jn[u] = cg[min((u << 6) + lane, nc - 1)];
+        for (int c0 = 0; c0 < nch; c0 += UNR) {
+            int j[UNR];
+            bool v[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                v[u] = ((c0 + u) << 6) + lane < nc;
+                j[u] = jn[u];
+            }
+            float4 pj[UNR]; // x, y, z, h
+#pragma unroll
+            for (int u = 0; u < UNR; u++) pj[u] = k.pos4[j[u]];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) jn[u] = cg[min(((c0 + UNR + u) << 6) + lane, nc - 1)];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                if (c0 + u >= nch) break;
+                const float r2f = r2_f32(pj[u].x, pj[u].y, pj[u].z, xf, yf, zf, Lf, wrap);
+                const float hmf = fmaxf(hf, pj[u].w);
+                const float hm2f = hmf * hmf;
+                const float E = 0x1p-19f * __builtin_fmaf(Lf, hmf, hm2f);
+                bool hit = r2f < hm2f - E;
+                const bool amb = v[u] && !hit && !(r2f > hm2f + E);
+                if (ballot(amb)) { // inside the band: the FP64 test decides
+                    if (amb) {
+                        const int jj = j[u];
+                        const double hm = fmax(M.h, k.g.h[jj]);
+                        hit = r2_of(k.g.x[jj], k.g.y[jj], k.g.z[jj], M.xi, M.yi, M.zi, M.bx.L, wrap) <
+                              hm * hm;
+                    }
+                }
+                const bool pair = v[u] && j[u] != M.i && hit;
+                ws.pairs += (unsigned)popc64(ballot(pair));
+                q.push(pair, HEnt{j[u]}, hp);
+            }
         }
-        // the r-th member is streamed by wave r mod GW
-        uint64_t rest = ev;
-        for (int r = 0; rest; r++) {
-            const int m = ctz64(rest);
-            rest &= rest - 1ull;
-            if (r % GW != wv) continue;
-            const int c = wrap ? hydro_emit<KER, ACC, true>(k, S, gc, s, bx.L, wrap, gm, m, fifo)
-                               : hydro_emit<KER, ACC, false>(k, S, gc, s, bx.L, wrap, gm, m, fifo);
-            ws.pairs += (unsigned long long)c;
-            ws.tests += (unsigned long long)s.nc;
-        }
+        q.flush(hp);
+        hydro_write<KER, ACC>(k, M.i, hp);
     }
     ws.flush(k.st);
 }
@@ -2550,6 +2501,7 @@ __device__ void verify_write(const VerK &k, int i, VerifyAcc &va)
 }
 
 struct VerVisit {
+    static constexpr int EB = 2; // leaf batches in flight (emit_leaves)
     const double *x, *y, *z, *h;
     double xi, yi, zi, L, hi;
     int i, mode;
@@ -2805,7 +2757,7 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.active = dp.reuse ? p.active : nullptr;
     k.dfr = sb.dfr;
     k.dstate = sb.dstate;
-    if ((e = launch_persistent(kg, s, k, 64 * GW, glds_bytes(k.C, false), sb.cu_count, p.n * GW)) !=
+    if ((e = launch_persistent(kg, s, k, 64 * GW, glds_bytes(k.C), sb.cu_count, p.n * GW)) !=
         hipSuccess)
         return e;
     ks<<<grid_s, 64 * MEM_WAVES, lds_s, s>>>(k);
@@ -2819,8 +2771,8 @@ template <int KER, typename ACC>
 hipError_t run_hydro(hipStream_t s, const HydroK &k, const SearchBufs &sb, int64_t n)
 {
     const size_t lds_s = (size_t)MEM_WAVES * HSOLO_WAVE_LDS;
-    hipError_t e = launch_persistent(k_hgrp<KER, ACC>, s, k, 64 * GW, glds_bytes(k.C, true),
-                                     sb.cu_count, n * GW);
+    hipError_t e = launch_persistent(k_hmem<KER, ACC>, s, k, 256, (size_t)MEM_WAVES * FIFO_BYTES,
+                                     sb.cu_count, n);
     if (e == hipSuccess)
         e = launch_persistent(k_hydro_solo<KER, ACC>, s, k, 64 * MEM_WAVES, lds_s, sb.cu_count, n);
     return e;
@@ -2874,7 +2826,6 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
-    k.C = hp.t_cand < GC_MAX ? hp.t_cand : GC_MAX;
     k.drift = hp.reuse ? sb.drift : nullptr;
     k.active = hp.reuse ? p.active : nullptr;
     k.dfr = sb.dfr;
