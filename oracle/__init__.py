@@ -90,6 +90,10 @@ def _declare(L):
     L.orc_hydro.restype = None
     L.orc_hydro.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32, _P,
                             _P, _I64, _P, _I32, _I32, _D, _D, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_hydro_prod.restype = None
+    L.orc_hydro_prod.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32,
+                                 _P, _P, _I64, _P, _I32, _I32, _D, _D, _D, _D, _D, _P, _P,
+                                 _P, _P, _P, _P, _P, _P, _P]
     L.orc_group_superset_size.restype = _I64
     L.orc_group_superset_size.argtypes = [_I64, _P, _P, _P, _P, _I32, _P, _P, _P, _I64,
                                           _I64, _D]
@@ -365,6 +369,38 @@ def hydro(x, y, z, h, m, vx, vy, vz, u, rho, fgrad, boxes: Boxes, targets, kerne
                      _ptr(t), int(use_grid), kernel, gamma, alpha, _ptr(r.ax), _ptr(r.ay),
                      _ptr(r.az), _ptr(r.dudt), _ptr(r.vsigmax), _ptr(r.abs_a),
                      _ptr(r.abs_du))
+    return r
+
+
+@dataclass
+class HydroProdResult:
+    ax: np.ndarray
+    ay: np.ndarray
+    az: np.ndarray
+    dudt: np.ndarray
+    vsigmax: np.ndarray
+    divv: np.ndarray
+    dalphadt: np.ndarray
+    abs_a: np.ndarray
+    abs_du: np.ndarray
+
+
+def hydro_prod(x, y, z, h, m, vx, vy, vz, u, rho, fgrad, alpha, boxes: Boxes, targets, kernel,
+               gamma=5.0 / 3.0, alpha_u=1.0, alpha_min=0.1, alpha_max=1.0, ell=0.1,
+               use_grid=False) -> HydroProdResult:
+    """Gadget3's production SPH (per-particle viscosity coefficient, artificial
+    conduction, velocity divergence and the viscosity switch's rate) for
+    each target; see orc_hydro_prod."""
+    arrs = [_c(a, np.float64) for a in (x, y, z, h, m, vx, vy, vz, u, rho, fgrad, alpha)]
+    t = _c(targets, np.int32)
+    nt = len(t)
+    r = HydroProdResult(*(np.empty(nt, np.float64) for _ in range(9)))
+    _lib().orc_hydro_prod(len(arrs[0]), *(_ptr(a) for a in arrs), boxes.nbox,
+                          _ptr(_c(boxes.off, np.int64)), _ptr(_c(boxes.L, np.float64)), nt,
+                          _ptr(t), int(use_grid), kernel, gamma, alpha_u, alpha_min, alpha_max,
+                          ell, _ptr(r.ax), _ptr(r.ay), _ptr(r.az), _ptr(r.dudt),
+                          _ptr(r.vsigmax), _ptr(r.divv), _ptr(r.dalphadt), _ptr(r.abs_a),
+                          _ptr(r.abs_du))
     return r
 
 
