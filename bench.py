@@ -294,7 +294,7 @@ def main():
             "traffic": traffic, "kernel": kname,
             "kernels": ("k_dens_prep + k_walk + k_dgrp + k_dens_solo"
                         if kname == "density"
-                        else "refit + k_hydro_prep + k_walk + k_hgrp + k_hydro_solo"),
+                        else "refit + k_hydro_prep + k_walk + k_hmem + k_hydro_solo"),
             "algorithmic_ops": int(kops),
             "ops_model": f"{TEST_OPS} per member x candidate test, {DENS_PAIR_OPS} per density "
                          f"pair, {HYD_PAIR_OPS} per hydro pair",

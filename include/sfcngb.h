@@ -278,27 +278,50 @@ typedef struct {
 SFC_API int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp,
             sfc_density_out *out);
 
+#define SFC_HYDRO_STANDARD 0   /* one viscosity coefficient alpha */
+#define SFC_HYDRO_PRODUCTION 1 /* Gadget3's production SPH, see hydro_force */
+
 typedef struct {
     int32_t kernel; /* SFC_KERNEL_* */
     double gamma;   /* adiabatic index */
-    double alpha;   /* artificial viscosity */
+    double alpha;   /* artificial viscosity (SFC_HYDRO_STANDARD) */
     int32_t accum;  /* SFC_ACCUM_* */
     int32_t t_cand; /* candidate tile */
     double skin;    /* group walk radius = R_g + (skin - 1) * max h + max(max h, h_j), skin >= 1 */
     int32_t reuse;  /* 1: filter the supersets kept by the last walking hydro call */
+    int32_t physics;           /* SFC_HYDRO_*; the fields below are read by SFC_HYDRO_PRODUCTION */
+    const float *alpha_i;      /* device [n]: each particle's viscosity coefficient (>= 0),
+                                  evolved in time by the caller from out->dalphadt */
+    double alpha_u;            /* artificial conduction coefficient (>= 0) */
+    double alpha_min, alpha_max; /* the viscosity switch's floor and ceiling */
+    double ell;                /* the switch's decay: rate ell * c_i / h_i (>= 0) */
 } sfc_hydro_params;
 
 typedef struct {
     float *ax, *ay, *az, *dudt, *vsigmax;     /* device [n] */
     double *ax64, *ay64, *az64, *dudt64;      /* device [n] or NULL (SFC_ACCUM_F64) */
+    float *divv, *dalphadt;                   /* device [n] or NULL (SFC_HYDRO_PRODUCTION):
+                                                 velocity divergence, d alpha_i / dt */
 } sfc_hydro_out;
 
 /* Hydro force over the active particles of the last group_ngb_search:
  * neighbours j != i closer than max(h_i, h_j) (section "Phases of Neighbour
  * Search"); SPH pressure force with artificial viscosity in the Gadget-2
- * form.  Requires vx, vy, vz, u, rho, fgrad.  First recomputes every node's
- * max h from p->h (h may have changed since the tree was built), then each
- * group walks once with R_g + max(max member h, h_j). */
+ * form:  P_i = (gamma - 1) rho_i u_i,  c_i = sqrt(gamma P_i / rho_i),
+ *   a_i = -sum_j m_j (f_i P_i/rho_i^2 W'_i + f_j P_j/rho_j^2 W'_j + Pi_ij W'_ij) x_ij / r,
+ *   du_i/dt = sum_j m_j (f_i P_i/rho_i^2 W'_i + Pi_ij W'_ij / 2) v_ij . x_ij / r,
+ * W'_i = dW(r, h_i)/dr, W'_ij = (W'_i + W'_j)/2, Pi_ij = -(alpha/2) v_sig w_ij / rho_ij,
+ * w_ij = min(v_ij . x_ij / r, 0), v_sig = c_i + c_j - 3 w_ij, rho_ij = (rho_i + rho_j)/2.
+ * SFC_HYDRO_PRODUCTION is Gadget3's production SPH after the scheme the
+ * paper cites for it in its introduction (no formula of it is printed in
+ * the paper): alpha is replaced by (alpha_i + alpha_j)/2, du_i/dt gains the
+ * artificial conduction sum_j m_j alpha_u sqrt(|P_i - P_j| / rho_ij)
+ * (u_i - u_j) W'_ij / rho_ij, and out->divv, out->dalphadt (when not NULL)
+ * receive div v_i = -(1/rho_i) sum_j m_j W'_i v_ij . x_ij / r and the switch's
+ * rate -(alpha_i - alpha_min) ell c_i / h_i + max(-div v_i, 0) (alpha_max - alpha_i).
+ * Requires vx, vy, vz, u, rho, fgrad.  First recomputes every node's max h
+ * from p->h (h may have changed since the tree was built), then each group
+ * walks once with R_g + max(max member h, h_j). */
 SFC_API int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp,
                 sfc_hydro_out *out);
 

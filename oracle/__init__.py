@@ -93,7 +93,7 @@ def _declare(L):
     L.orc_hydro_prod.restype = None
     L.orc_hydro_prod.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I32,
                                  _P, _P, _I64, _P, _I32, _I32, _D, _D, _D, _D, _D, _P, _P,
-                                 _P, _P, _P, _P, _P, _P, _P]
+                                 _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_group_superset_size.restype = _I64
     L.orc_group_superset_size.argtypes = [_I64, _P, _P, _P, _P, _I32, _P, _P, _P, _I64,
                                           _I64, _D]
@@ -383,6 +383,7 @@ class HydroProdResult:
     dalphadt: np.ndarray
     abs_a: np.ndarray
     abs_du: np.ndarray
+    abs_divv: np.ndarray  # sum of the divergence terms' magnitudes over rho_i
 
 
 def hydro_prod(x, y, z, h, m, vx, vy, vz, u, rho, fgrad, alpha, boxes: Boxes, targets, kernel,
@@ -394,13 +395,13 @@ def hydro_prod(x, y, z, h, m, vx, vy, vz, u, rho, fgrad, alpha, boxes: Boxes, ta
     arrs = [_c(a, np.float64) for a in (x, y, z, h, m, vx, vy, vz, u, rho, fgrad, alpha)]
     t = _c(targets, np.int32)
     nt = len(t)
-    r = HydroProdResult(*(np.empty(nt, np.float64) for _ in range(9)))
+    r = HydroProdResult(*(np.empty(nt, np.float64) for _ in range(10)))
     _lib().orc_hydro_prod(len(arrs[0]), *(_ptr(a) for a in arrs), boxes.nbox,
                           _ptr(_c(boxes.off, np.int64)), _ptr(_c(boxes.L, np.float64)), nt,
                           _ptr(t), int(use_grid), kernel, gamma, alpha_u, alpha_min, alpha_max,
                           ell, _ptr(r.ax), _ptr(r.ay), _ptr(r.az), _ptr(r.dudt),
                           _ptr(r.vsigmax), _ptr(r.divv), _ptr(r.dalphadt), _ptr(r.abs_a),
-                          _ptr(r.abs_du))
+                          _ptr(r.abs_du), _ptr(r.abs_divv))
     return r
 
 

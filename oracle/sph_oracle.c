@@ -859,7 +859,7 @@ void orc_hydro_prod(int64_t n, const double *x, const double *y, const double *z
                     int32_t kernel, double gamma, double alpha_u, double alpha_min,
                     double alpha_max, double ell, double *ax, double *ay, double *az,
                     double *dudt, double *vsigmax, double *divv, double *dalphadt,
-                    double *abs_a, double *abs_du)
+                    double *abs_a, double *abs_du, double *abs_divv)
 {
     (void)n;
     orc_space s;
@@ -881,7 +881,8 @@ void orc_hydro_prod(int64_t n, const double *x, const double *y, const double *z
             double Pi = (gamma - 1.0) * rho[i] * u[i];
             double ci = sqrt(gamma * Pi / rho[i]);
             double Pfi = fgrad[i] * Pi / (rho[i] * rho[i]);
-            double sax = 0, say = 0, saz = 0, sdu = 0, vmax = 0, sabs = 0, sdabs = 0, sdiv = 0;
+            double sax = 0, say = 0, saz = 0, sdu = 0, vmax = 0, sabs = 0, sdabs = 0, sdiv = 0,
+                   sdivabs = 0;
             ORC_FOR_CAND(mm, b0, b1, scr, j, {
                 double dx = orc_fold(x[i] - x[j], L);
                 double dy = orc_fold(y[i] - y[j], L);
@@ -917,6 +918,7 @@ void orc_hydro_prod(int64_t n, const double *x, const double *y, const double *z
                         double d3 = m[j] * alpha_u * vu * (u[i] - u[j]) * dWb / rhob;
                         sdu += d1 + d2 + d3;
                         sdiv += m[j] * (vr / r) * dWi;
+                        sdivabs += fabs(m[j] * (vr / r) * dWi);
                         sabs += fabs(fac);
                         sdabs += fabs(d1) + fabs(d2) + fabs(d3);
                         if (vsig > vmax) vmax = vsig;
@@ -937,6 +939,7 @@ void orc_hydro_prod(int64_t n, const double *x, const double *y, const double *z
                           (dv < 0.0 ? -dv : 0.0) * (alpha_max - alpha_p[i]);
             if (abs_a) abs_a[t] = sabs;
             if (abs_du) abs_du[t] = sdabs;
+            if (abs_divv) abs_divv[t] = sdivabs / rho[i];
         }
         free(scr.buf);
     }

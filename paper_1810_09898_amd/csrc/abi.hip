@@ -198,6 +198,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     xb.grp = b.take<int32_t>(n);
     xb.pa = b.take<float4>(n);
     xb.pb = b.take<float4>(n);
+    xb.pc = b.take<float4>(n);
     xb.pos4 = b.take<float4>(n);
     xb.p64 = b.take<double4>(n);
     xb.dstate = b.take<double4>(n);
@@ -595,6 +596,14 @@ int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp
     if ((r = check_tile(ctx, hp->t_cand))) return r;
     if (!(hp->skin >= 1.0 && hp->skin <= 4.0))
         return fail(ctx, SFC_EINVAL, "hydro_force: skin must be in [1, 4]");
+    if (hp->physics != SFC_HYDRO_STANDARD && hp->physics != SFC_HYDRO_PRODUCTION)
+        return fail(ctx, SFC_EINVAL, "hydro_force: bad physics %d", hp->physics);
+    if (hp->physics == SFC_HYDRO_PRODUCTION &&
+        (!hp->alpha_i || !(hp->alpha_u >= 0.0) || !(hp->alpha_min >= 0.0) ||
+         !(hp->alpha_max >= hp->alpha_min) || !(hp->ell >= 0.0)))
+        return fail(ctx, SFC_EINVAL,
+                    "hydro_force: production physics needs alpha_i, alpha_u >= 0, "
+                    "0 <= alpha_min <= alpha_max and ell >= 0");
     if (hp->reuse != 0 && hp->reuse != 1)
         return fail(ctx, SFC_EINVAL, "hydro_force: reuse must be 0 or 1");
     if (hp->reuse && ctx->kept_h == 0)

@@ -266,6 +266,7 @@ struct SearchBufs {
     GSup *sup;        // [n] per group
     int32_t *grp;     // [n] per active: its group
     float4 *pa, *pb;  // [n] hydro records: (m, v) and (rho, f P / rho^2, c, h)
+    float4 *pc;       // [n] production SPH: (alpha_i, u, P)
     float4 *pos4;     // [n] FP32 x, y, z and (density) m or (hydro) h, for the walks
     double4 *p64;     // [n] FP64 x, y, z, h: the group filters and the pair terms
     double4 *dstate;  // [n] per active: h, bracket lo, hi, evaluations (members that leave

@@ -135,6 +135,19 @@ template <typename T> __device__ __forceinline__ T acc_rcp(T x);
 template <> __device__ __forceinline__ float acc_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double acc_rcp<double>(double x) { return 1.0 / x; }
 
+// the same from the FP64 difference h^2 - r^2 already rounded to T
+template <typename T> __device__ __forceinline__ T tail_g(T d, T inv_h2, T q);
+template <> __device__ __forceinline__ float tail_g<float>(float d, float inv_h2, float q)
+{
+    return d > 0.0f ? d * inv_h2 * __builtin_amdgcn_rcpf(1.0f + q) : 0.0f;
+}
+template <> __device__ __forceinline__ double tail_g<double>(double d, double inv_h2, double q)
+{
+    (void)d;
+    (void)inv_h2;
+    return q < 1.0 ? 1.0 - q : 0.0;
+}
+
 template <typename T> struct Kahan {
     T s = T(0), c = T(0);
     __device__ __forceinline__ void add(T v)
@@ -2064,45 +2077,77 @@ struct HydroK {
     sfc_hydro_out out;
     DevStatus *st;
     double gamma, alpha;
+    // production SPH: per particle (alpha_i, u, P) in pc, conduction, switch
+    const float4 *pc;
+    const float *alpha_i;
+    double alpha_u, alpha_min, alpha_max, ell;
 };
 
 namespace {
-template <int KER, typename ACC> struct HydroAcc {
+// PHYS 0: the standard force; 1: the production SPH (a per-particle
+// viscosity coefficient, artificial conduction, the velocity divergence)
+template <int KER, typename ACC, int PHYS = 0> struct HydroAcc {
+    static constexpr int phys = PHYS;
     const HydroK *k;
     double xi, yi, zi, L;
     bool wrap;
     double h2;
     ACC hinv, hinv4, vx, vy, vz, rho, pf, cs;
-    Kahan<ACC> ax, ay, az, du;
+    ACC al, ui, Pi; // production: alpha_i, u_i, P_i
+    Kahan<ACC> ax, ay, az, du, dv;
     ACC vmax;
     struct Term {
-        ACC ax, ay, az, du, vs;
+        ACC ax, ay, az, du, vs, dv;
     };
-    // the pair term of neighbour j with FP64 position and h pj
-    __device__ __forceinline__ Term make(int j, const double4 &pj) const
+    // the pair geometry from the neighbour's FP64 position and h: x_i - x_j
+    // (the force direction) and r^2 in FP64 rounded once, and the FP64
+    // differences h_i^2 - r^2, h_j^2 - r^2 rounded once (the kernel tails)
+    struct Geo {
+        ACC dx, dy, dz, r2, ti, tj;
+    };
+    __device__ __forceinline__ Geo geom(const double4 &pj) const
     {
-        constexpr ACC C = (ACC)knorm<KER>();
-        // x_i - x_j (the force direction) in FP64, rounded once for FP32
         double dxd = xi - pj.x, dyd = yi - pj.y, dzd = zi - pj.z;
         if (wrap) {
             dxd = fold(dxd, L);
             dyd = fold(dyd, L);
             dzd = fold(dzd, L);
         }
-        const ACC dx = (ACC)dxd, dy = (ACC)dyd, dz = (ACC)dzd;
         const double r2d = __builtin_fma(dzd, dzd, __builtin_fma(dyd, dyd, dxd * dxd));
+        Geo g;
+        g.dx = (ACC)dxd;
+        g.dy = (ACC)dyd;
+        g.dz = (ACC)dzd;
+        g.r2 = (ACC)r2d;
+        g.ti = (ACC)(h2 - r2d);
+        g.tj = (ACC)(pj.w * pj.w - r2d);
+        return g;
+    }
+    __device__ __forceinline__ Term make(int j, const double4 &pj) const { return make_g(j, geom(pj), pj.w); }
+    // the pair term of neighbour j from its geometry (hj64: its FP64 h, read
+    // by the FP64 variant only)
+    __device__ __forceinline__ Term make_g(int j, const Geo &g, double hj64) const
+    {
+        constexpr ACC C = (ACC)knorm<KER>();
+        const ACC dx = g.dx, dy = g.dy, dz = g.dz;
         ACC mj, vxj, vyj, vzj, rhoj, pfj, csj, hj;
+        ACC alj = ACC(0), uj = ACC(0), Pj = ACC(0);
         if (sizeof(ACC) == 8) {
             double gm1 = k->gamma - 1.0;
-            double uj = k->u[j];
+            double ujd = k->u[j];
             rhoj = (ACC)k->rho[j];
-            pfj = (ACC)(k->fgrad[j] * gm1 * uj / (double)k->rho[j]);
-            csj = (ACC)sqrt(k->gamma * gm1 * uj);
-            hj = (ACC)pj.w;
+            pfj = (ACC)(k->fgrad[j] * gm1 * ujd / (double)k->rho[j]);
+            csj = (ACC)sqrt(k->gamma * gm1 * ujd);
+            hj = (ACC)hj64;
             mj = (ACC)k->m[j];
             vxj = (ACC)k->vx[j];
             vyj = (ACC)k->vy[j];
             vzj = (ACC)k->vz[j];
+            if (PHYS) {
+                alj = (ACC)k->alpha_i[j];
+                uj = (ACC)ujd;
+                Pj = (ACC)(gm1 * (double)k->rho[j] * ujd);
+            }
         } else {
             const float4 a = k->pa[j];
             const float4 b = k->pb[j];
@@ -2114,14 +2159,20 @@ template <int KER, typename ACC> struct HydroAcc {
             pfj = (ACC)b.y;
             csj = (ACC)b.z;
             hj = (ACC)b.w;
+            if (PHYS) {
+                const float4 c = k->pc[j];
+                alj = (ACC)c.x;
+                uj = (ACC)c.y;
+                Pj = (ACC)c.z;
+            }
         }
-        ACC r = acc_sqrt((ACC)r2d);
+        ACC r = acc_sqrt(g.r2);
         ACC rinv = r > ACC(0) ? acc_rcp(r) : ACC(0);
         const ACC qi = r * hinv;
-        const ACC dwi = kern_deval_u<KER, ACC>(qi, tail_u<ACC>(h2, r2d, hinv * hinv, qi));
+        const ACC dwi = kern_deval_u<KER, ACC>(qi, tail_g<ACC>(g.ti, hinv * hinv, qi));
         ACC hjinv = acc_rcp(hj);
         const ACC qj = r * hjinv;
-        const ACC dwj = kern_deval_u<KER, ACC>(qj, tail_u<ACC>(pj.w * pj.w, r2d, hjinv * hjinv, qj));
+        const ACC dwj = kern_deval_u<KER, ACC>(qj, tail_g<ACC>(g.tj, hjinv * hjinv, qj));
         ACC hj2 = hjinv * hjinv;
         ACC dWi = C * dwi * hinv4;
         ACC dWj = C * dwj * (hj2 * hj2);
@@ -2130,7 +2181,9 @@ template <int KER, typename ACC> struct HydroAcc {
         ACC vr = mad(vdz, dz, mad(vdy, dy, vdx * dx));
         ACC wij = vr < ACC(0) ? vr * rinv : ACC(0);
         ACC vsig = cs + csj - ACC(3) * wij;
-        ACC visc = -(ACC)k->alpha * vsig * wij * acc_rcp(rho + rhoj);
+        const ACC rr = acc_rcp(rho + rhoj); // 1 / (2 rho_ij)
+        const ACC aij = PHYS ? ACC(0.5) * (al + alj) : (ACC)k->alpha;
+        ACC visc = -aij * vsig * wij * rr;
         ACC fac = mj * (pf * dWi + pfj * dWj + visc * dWb);
         ACC fr = fac * rinv;
         Term t;
@@ -2139,6 +2192,13 @@ template <int KER, typename ACC> struct HydroAcc {
         t.az = -fr * dz;
         t.du = mj * (pf * dWi + ACC(0.5) * visc * dWb) * vr * rinv;
         t.vs = vsig;
+        t.dv = ACC(0);
+        if (PHYS) {
+            // conduction at the signal speed sqrt(|P_i - P_j| / rho_ij)
+            const ACC vu = acc_sqrt(fabs(Pi - Pj) * ACC(2) * rr);
+            t.du += mj * (ACC)k->alpha_u * vu * (ui - uj) * dWb * ACC(2) * rr;
+            t.dv = mj * vr * rinv * dWi;
+        }
         return t;
     }
     __device__ __forceinline__ void add(const Term &t)
@@ -2147,6 +2207,7 @@ template <int KER, typename ACC> struct HydroAcc {
         ay.add(t.ay);
         az.add(t.az);
         du.add(t.du);
+        if (PHYS) dv.add(t.dv);
         vmax = t.vs > vmax ? t.vs : vmax;
     }
     __device__ __forceinline__ void init(const HydroK &kk, int i, double x, double y, double z,
@@ -2171,12 +2232,18 @@ template <int KER, typename ACC> struct HydroAcc {
         pf = (ACC)(kk.fgrad[i] * gm1 * u / (double)kk.rho[i]);
         cs = (ACC)sqrt(kk.gamma * gm1 * u);
         vmax = ACC(0);
+        al = ui = Pi = ACC(0);
+        if (PHYS) {
+            al = (ACC)kk.alpha_i[i];
+            ui = (ACC)u;
+            Pi = (ACC)(gm1 * (double)kk.rho[i] * u);
+        }
     }
 };
 
 // neighbours given by particle index
-template <int KER, typename ACC> struct HydroPair : HydroAcc<KER, ACC> {
-    using Term = typename HydroAcc<KER, ACC>::Term;
+template <int KER, typename ACC, int PHYS = 0> struct HydroPair : HydroAcc<KER, ACC, PHYS> {
+    using Term = typename HydroAcc<KER, ACC, PHYS>::Term;
     __device__ __forceinline__ Term term(const HEnt &e) const
     {
         return this->make(e.j, this->k->p64[e.j]);
@@ -2184,11 +2251,12 @@ template <int KER, typename ACC> struct HydroPair : HydroAcc<KER, ACC> {
 };
 
 
-template <int KER, typename ACC>
-__device__ __forceinline__ HydroPair<KER, ACC> hydro_pair(const HydroK &k, int i, double xi, double yi,
-                                                          double zi, double L, double h, bool wrap)
+template <int KER, typename ACC, int PHYS>
+__device__ __forceinline__ HydroPair<KER, ACC, PHYS> hydro_pair(const HydroK &k, int i, double xi,
+                                                                double yi, double zi, double L,
+                                                                double h, bool wrap)
 {
-    HydroPair<KER, ACC> hp;
+    HydroPair<KER, ACC, PHYS> hp;
     hp.init(k, i, xi, yi, zi, L, h, wrap);
     return hp;
 }
@@ -2200,6 +2268,8 @@ __device__ void hydro_write(const HydroK &k, int i, const P &hp)
     double ay = (double)wave_sum_f_or_d(hp.ay.value());
     double az = (double)wave_sum_f_or_d(hp.az.value());
     double du = (double)wave_sum_f_or_d(hp.du.value());
+    double dvs = 0.0;
+    if (P::phys) dvs = (double)wave_sum_f_or_d(hp.dv.value());
     ACC vm = hp.vmax;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -2207,6 +2277,16 @@ __device__ void hydro_write(const HydroK &k, int i, const P &hp)
         vm = t > vm ? t : vm;
     }
     if (lane_id() != 0) return;
+    if (P::phys) {
+        // the velocity divergence and the viscosity switch's rate
+        const double divv = -dvs / (double)k.rho[i];
+        const double al = (double)k.alpha_i[i];
+        const double c = sqrt(k.gamma * (k.gamma - 1.0) * (double)k.u[i]);
+        const double rate = -(al - k.alpha_min) * k.ell * c / k.g.h[i] +
+                            (divv < 0.0 ? -divv : 0.0) * (k.alpha_max - al);
+        if (k.out.divv) k.out.divv[i] = (float)divv;
+        if (k.out.dalphadt) k.out.dalphadt[i] = (float)rate;
+    }
     k.out.ax[i] = (float)ax;
     k.out.ay[i] = (float)ay;
     k.out.az[i] = (float)az;
@@ -2316,7 +2396,8 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
                              const double *__restrict__ x, const double *__restrict__ y,
                              const double *__restrict__ z, double gamma, float4 *__restrict__ pa,
                              float4 *__restrict__ pb, float4 *__restrict__ pos4,
-                             double4 *__restrict__ p64, double4 *__restrict__ snap)
+                             double4 *__restrict__ p64, double4 *__restrict__ snap,
+                             const float *__restrict__ alpha_i, float4 *__restrict__ pc)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -2329,6 +2410,8 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
     p64[i] = make_double4(xi, yi, zi, hi);
     pb[i] = make_float4(rho[i], (float)(fgrad[i] * gm1 * uu / (double)rho[i]),
                         (float)sqrt(gamma * gm1 * uu), (float)hi);
+    // production SPH: alpha_i, u_i, P_i
+    if (alpha_i) pc[i] = make_float4(alpha_i[i], (float)uu, (float)(gm1 * (double)rho[i] * uu), 0.0f);
 }
 
 
@@ -2337,8 +2420,8 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
 // that is safely away from the edge and by the FP64 test inside the band,
 // the pairs streamed through the FIFO into the force sums.  Members the
 // superset does not cover are listed for k_hydro_solo.
-template <int KER, typename ACC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? 5 : 1))) void k_hmem(HydroK k)
+template <int KER, typename ACC, int PHYS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? (PHYS ? 4 : 5) : 1))) void k_hmem(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     HEnt *fifo = (HEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
@@ -2359,7 +2442,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
             continue;
         }
         const bool wrap = (M.s.flags & GSUP_WRAP) || k.drift;
-        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M.i, M.xi, M.yi, M.zi, M.bx.L, M.h, wrap);
+        HydroPair<KER, ACC, PHYS> hp = hydro_pair<KER, ACC, PHYS>(k, M.i, M.xi, M.yi, M.zi, M.bx.L, M.h,
+                                                                  wrap);
         FifoH q{fifo, 0};
         // the FP32 screen: coordinates off by at most 2^-24 L each, h by
         // 2^-24 h; near r = max(h_i, h_j) the FP32 r^2 is within
@@ -2418,7 +2502,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
 // kept none, or a reused one no longer covers them): one wave each walks the
 // tree level by level and streams its pairs into the sums.
 constexpr int HSOLO_WAVE_LDS = FIFO_BYTES + 4 * (2 * LCAP + 64);
-template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro_solo(HydroK k)
+template <int KER, typename ACC, int PHYS> __global__ __launch_bounds__(256) void k_hydro_solo(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const int wave = uni((int)(threadIdx.x >> 6));
@@ -2432,8 +2516,9 @@ template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_hydro_
     WaveStats ws;
     for (int item = ar.i; item < ar.end; item += ar.stride) {
         const Member M = member(k.g, k.ga, k.ca, uni(k.dfr[item]));
-        HydroPair<KER, ACC> hp = hydro_pair<KER, ACC>(k, M.i, M.xi, M.yi, M.zi, M.bx.L, M.h, true);
-        StreamVisit<1, HydroPair<KER, ACC>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
+        HydroPair<KER, ACC, PHYS> hp = hydro_pair<KER, ACC, PHYS>(k, M.i, M.xi, M.yi, M.zi, M.bx.L, M.h,
+                                                                  true);
+        StreamVisit<1, HydroPair<KER, ACC, PHYS>, FifoH> sv{k.g.x, k.g.y, k.g.z, k.g.h, M.xi, M.yi, M.zi,
                                                M.bx.L, M.h, M.i, FifoH{(HEnt *)S.fifo, 0}, &hp};
         Ball B{M.xi, M.yi, M.zi, M.bx.L, 0.0, 0.0, M.h, 1};
         solo_walk(k.g, S, M, B, sv, k.st);
@@ -2692,9 +2777,9 @@ hipError_t launch_drift(hipStream_t s, const PartDev &p, const double *h, const 
     return hipGetLastError();
 }
 
-// The density pass: the walk of the groups, k_dgroup (the h loop of every
-// group's members on its superset), k_dens_solo (the members that left their
-// group superset) and k_dsum (the sums of the others).  Each wave of
+// The density pass: the walk of the groups, k_dgrp (the h loop and the sums
+// of every group's members on its superset, one workgroup per group) and
+// k_dens_solo (the members that left their group superset).  Each wave of
 // k_dens_solo owns a private slot of T candidates at the end of the
 // candidate buffer (when the slots take at most half of it); the group
 // supersets use the rest.
@@ -2767,14 +2852,15 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     return hipGetLastError();
 }
 
-template <int KER, typename ACC>
+template <int KER, typename ACC, int PHYS>
 hipError_t run_hydro(hipStream_t s, const HydroK &k, const SearchBufs &sb, int64_t n)
 {
     const size_t lds_s = (size_t)MEM_WAVES * HSOLO_WAVE_LDS;
-    hipError_t e = launch_persistent(k_hmem<KER, ACC>, s, k, 256, (size_t)MEM_WAVES * FIFO_BYTES,
+    hipError_t e = launch_persistent(k_hmem<KER, ACC, PHYS>, s, k, 256, (size_t)MEM_WAVES * FIFO_BYTES,
                                      sb.cu_count, n);
     if (e == hipSuccess)
-        e = launch_persistent(k_hydro_solo<KER, ACC>, s, k, 64 * MEM_WAVES, lds_s, sb.cu_count, n);
+        e = launch_persistent(k_hydro_solo<KER, ACC, PHYS>, s, k, 64 * MEM_WAVES, lds_s, sb.cu_count,
+                              n);
     return e;
 }
 } // namespace
@@ -2796,7 +2882,11 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k_hydro_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.m, p.vx, p.vy, p.vz, p.rho,
                                                                p.fgrad, p.u, p.h, p.x, p.y, p.z,
                                                                hp.gamma, sb.pa, sb.pb, sb.pos4,
-                                                               sb.p64, a.keep ? sb.snap : nullptr);
+                                                               sb.p64, a.keep ? sb.snap : nullptr,
+                                                               hp.physics == SFC_HYDRO_PRODUCTION
+                                                                   ? hp.alpha_i
+                                                                   : nullptr,
+                                                               sb.pc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (hp.reuse) {
@@ -2826,14 +2916,24 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
+    k.pc = sb.pc;
+    k.alpha_i = hp.alpha_i;
+    k.alpha_u = hp.alpha_u;
+    k.alpha_min = hp.alpha_min;
+    k.alpha_max = hp.alpha_max;
+    k.ell = hp.ell;
     k.drift = hp.reuse ? sb.drift : nullptr;
     k.active = hp.reuse ? p.active : nullptr;
     k.dfr = sb.dfr;
     const int64_t n = p.n;
-    if (hp.kernel == 0 && hp.accum == SFC_ACCUM_F32) e = run_hydro<0, float>(s, k, sb, n);
-    else if (hp.kernel == 0) e = run_hydro<0, double>(s, k, sb, n);
-    else if (hp.accum == SFC_ACCUM_F32) e = run_hydro<1, float>(s, k, sb, n);
-    else e = run_hydro<1, double>(s, k, sb, n);
+    const bool f32 = hp.accum == SFC_ACCUM_F32;
+    if (hp.physics == SFC_HYDRO_PRODUCTION) {
+        if (hp.kernel == 0) e = f32 ? run_hydro<0, float, 1>(s, k, sb, n) : run_hydro<0, double, 1>(s, k, sb, n);
+        else e = f32 ? run_hydro<1, float, 1>(s, k, sb, n) : run_hydro<1, double, 1>(s, k, sb, n);
+    } else {
+        if (hp.kernel == 0) e = f32 ? run_hydro<0, float, 0>(s, k, sb, n) : run_hydro<0, double, 0>(s, k, sb, n);
+        else e = f32 ? run_hydro<1, float, 0>(s, k, sb, n) : run_hydro<1, double, 0>(s, k, sb, n);
+    }
     if (e != hipSuccess || !hp.reuse) return e;
     k_reuse_check<<<1, 64, 0, s>>>(sb.drift, st);
     return hipGetLastError();

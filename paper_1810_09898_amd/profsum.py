@@ -74,7 +74,7 @@ def _dispatches(rows):
 
 DENS_CALL = ("k_dens_prep", "k_reset_pass", "k_walk", "k_dgrp")
 HYDRO_CALL = ("k_tree_leaves", "k_tree_up3", "k_tree_nchild", "k_hydro_prep", "k_reset_pass",
-              "k_walk", "k_hgrp")
+              "k_walk", "k_hmem")
 
 
 def _calls(disp):

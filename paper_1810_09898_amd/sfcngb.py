@@ -20,6 +20,7 @@ SFC_OK, SFC_EINVAL, SFC_EWORKSPACE, SFC_EHIP, SFC_EOVERFLOW, SFC_EORDER = 0, -1,
 POLICY_COUNT, POLICY_PAPER, POLICY_TREE = 0, 1, 2
 KERNEL_CUBIC, KERNEL_WC6 = 0, 1
 ACCUM_F32, ACCUM_F64 = 0, 1
+HYDRO_STANDARD, HYDRO_PRODUCTION = 0, 1
 SORT_STATIC_MAX_N = 262144
 ST_LIST_OVERFLOW, ST_NODE_OVERFLOW, ST_BAD_INPUT, ST_GUARD, ST_REUSE_ACTIVE = 1, 2, 4, 8, 16
 
@@ -78,7 +79,9 @@ class DensityOut(C.Structure):
 class HydroParams(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("gamma", C.c_double), ("alpha", C.c_double),
                 ("accum", C.c_int32), ("t_cand", C.c_int32), ("skin", C.c_double),
-                ("reuse", C.c_int32)]
+                ("reuse", C.c_int32), ("physics", C.c_int32), ("alpha_i", _P),
+                ("alpha_u", C.c_double), ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+                ("ell", C.c_double)]
 
     def __init__(self, *args, **kw):
         if len(args) < 6:  # skin defaults to 1 (a group ball of R_g + max h)
@@ -88,7 +91,8 @@ class HydroParams(C.Structure):
 
 class HydroOut(C.Structure):
     _fields_ = [("ax", _P), ("ay", _P), ("az", _P), ("dudt", _P), ("vsigmax", _P),
-                ("ax64", _P), ("ay64", _P), ("az64", _P), ("dudt64", _P)]
+                ("ax64", _P), ("ay64", _P), ("az64", _P), ("dudt64", _P),
+                ("divv", _P), ("dalphadt", _P)]
 
 
 class Status(C.Structure):
