@@ -66,7 +66,9 @@ SFC_API int32_t sfc_ctx_cu_count(const sfc_ctx *ctx);
 
 /* Sizes that fix the workspace layout. */
 typedef struct {
-    int64_t n;           /* particles over all boxes, >= 1, < 2^31 */
+    int64_t n;           /* particles over all boxes, >= 1, < 2^30; the octree's node
+                            capacity, n + 22 n / (n_leaf_min + 1) + n_boxes + 64, must
+                            stay below 2^28 (SFC_EINVAL otherwise) */
     int32_t n_boxes;     /* >= 1 */
     int32_t n_leaf_min;  /* smallest leaf size tree_build will be given (>= 1) */
     int32_t t_cand_max;  /* largest candidate tile any call will use (64..8192, multiple of 64) */

@@ -147,7 +147,7 @@ bool dims_ok(const sfc_dims *d)
            d->t_cand_max >= 64 && d->t_cand_max <= 8192 && d->t_cand_max % 64 == 0 &&
            d->cand_per_particle >= 0 && d->cand_per_particle <= 4096 &&
            (d->keep_supersets == 0 || d->keep_supersets == 1) &&
-           node_capacity(*d) < ((int64_t)1 << 31) - 1;
+           node_capacity(*d) <= TREE_ITEM_NODE;
 }
 
 size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
@@ -173,6 +173,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     td.hi = b.take<double4>(cap);
     td.box32 = b.take<float4>(2 * cap);
     td.nchild = b.take<int32_t>(cap);
+    td.krec = b.take<float4>(16 * cap);
     td.box_root = b.take<int32_t>(nb + 1);
     td.capacity = (int32_t)cap;
     GroupBufs gb;

@@ -8,6 +8,8 @@
 #include "../../include/sfcngb.h"
 
 #define SFC_KEY_BITS 21
+// node indices fit in the 28 low bits of a walk item
+#define TREE_ITEM_NODE 0x0fffffff
 #define SFC_WG 256 // threads per workgroup in the persistent kernels (4 waves)
 
 // cell of a coordinate along one axis at the deepest level: floor(x/L 2^21),
@@ -166,6 +168,11 @@ struct TreeDev {
     float4 *box32;  // [2 * capacity]: the box in FP32 rounded outwards (min down, max and
                     // max h up): (min x, min y, min z, max h), (max x, max y, max z, 0)
     int32_t *nchild;
+    // [16 * capacity]: for child slot s of node p, at 2 (8 p + s), the child's
+    // FP32 box as in box32, with the .w of the second float4 holding the
+    // child's item (bit pattern of an int: node index | (child count - 1)
+    // << 28, leaf flag in bit 31); empty slots hold a box no ball reaches
+    float4 *krec;
     int32_t *box_root; // [nb+1]
     int32_t capacity;
 };
@@ -268,7 +275,8 @@ struct SearchBufs {
     float4 *pa, *pb;  // [n] hydro records: (m, v) and (rho, f P / rho^2, c, h)
     float4 *pc;       // [n] production SPH: (alpha_i, u, P)
     float4 *pos4;     // [n] FP32 x, y, z and (density) m or (hydro) h, for the walks
-    double4 *p64;     // [n] FP64 x, y, z, h: the group filters and the pair terms
+    double4 *p64;     // [n] FP64 x, y, z and the mass (density: group staging, pair
+                      // terms) or h (hydro: pair terms)
     double4 *dstate;  // [n] per active: h, bracket lo, hi, evaluations (members that leave
                       // their group superset)
     double4 *snap;    // [n] kept supersets: x, y, z (and h) when they were walked, or NULL

@@ -225,6 +225,7 @@ struct Geom {
     const int4 *info;
     const double4 *lo, *hi;
     const float4 *box32; // node boxes in FP32, rounded outwards
+    const float4 *krec;  // per child slot: the child's FP32 box and its item (tree.hip)
     const int32_t *kids, *nchild;
     const int32_t *box_root;
     int nb;
@@ -420,9 +421,8 @@ __device__ __forceinline__ float axis_gap32(float c, float lo, float hi, float L
     d = fminf(d, b + L);
     return d;
 }
-__device__ __forceinline__ bool node_open(const Geom &g, int c, const Ball &B)
+__device__ __forceinline__ bool box_open(const float4 &lo, const float4 &hi, const Ball &B)
 {
-    const float4 lo = g.box32[2 * (int64_t)c], hi = g.box32[2 * (int64_t)c + 1];
     const float L = (float)B.L;
     const float gx = axis_gap32((float)B.cx, lo.x, hi.x, L);
     const float gy = axis_gap32((float)B.cy, lo.y, hi.y, L);
@@ -438,28 +438,50 @@ __device__ __forceinline__ bool node_open(const Geom &g, int c, const Ball &B)
     }
     return d2 < lim;
 }
+__device__ __forceinline__ bool node_open(const Geom &g, int c, const Ball &B)
+{
+    return box_open(g.box32[2 * (int64_t)c], g.box32[2 * (int64_t)c + 1], B);
+}
 
-// Entry node of a walk: from the root, step down while exactly one child of
-// the current node is reached by the ball; every node the ball reaches then
-// lies in the entry node's subtree, [entry, skip(entry)).  Lanes 0-7 test the
-// children of the current node together.
+// The item of a node in the walks' lists: its index, its child count less
+// one, and a leaf flag in the sign bit (the format of the child records).
+__device__ __forceinline__ int item_node(int it) { return it & TREE_ITEM_NODE; }
+__device__ __forceinline__ int item_kids(int it) { return ((it >> 28) & 7) + 1; }
+__device__ __forceinline__ int root_item(const Geom &g, int root)
+{
+    const int4 ir = g.info[root];
+    const int nc = g.nchild[root];
+    return (ir.w >> 8) ? (root | (int)0x80000000u) : (root | ((max(nc, 1) - 1) << 28));
+}
+
+// Entry node of a walk (its item): from the root, step down while exactly
+// one child of the current node is reached by the ball; every node the ball
+// reaches then lies in the entry node's subtree, [entry, skip(entry)).  Lanes
+// 0-7 test the children of the current node together, on the child records
+// of the node (one load per level).
 __device__ __forceinline__ int walk_entry(const Geom &g, int root, const Ball &B)
 {
     const int lane = lane_id();
-    int p = root;
+    int it = uni(root_item(g, root));
 #pragma unroll 1
     for (int d = 0; d < 24; d++) { // 21 key levels below a root
-        const int4 ip = g.info[p];
-        if (ip.w >> 8) break;
-        const int c = lane < 8 ? g.kids[8 * (int64_t)p + lane] : -1;
-        const bool open = c >= 0 && node_open(g, c, B);
+        if (it < 0) break;         // a leaf
+        const int p = item_node(it);
+        bool open = false;
+        int ci = -1;
+        if (lane < item_kids(it)) {
+            const int64_t r = 2 * (8 * (int64_t)p + lane);
+            const float4 lo = g.krec[r], hi = g.krec[r + 1];
+            open = box_open(lo, hi, B);
+            ci = __float_as_int(hi.w);
+        }
         const uint64_t m = ballot(open);
         if (popc64(m) != 1) break;
-        const int nc = uni(readlane_i(c, ctz64(m)));
-        if (nc <= p) break; // a child always follows its parent
-        p = nc;
+        const int nit = uni(readlane_i(ci, ctz64(m)));
+        if (item_node(nit) <= p) break; // a child always follows its parent
+        it = nit;
     }
-    return p;
+    return it;
 }
 
 template <class V>
@@ -467,7 +489,7 @@ __device__ void walk(const Geom &g, int root, int root_end, const Ball &B, V &vi
                      DevStatus *st)
 {
     const int lane = lane_id();
-    int k = uni(walk_entry(g, uni(root), B));
+    int k = uni(item_node(walk_entry(g, uni(root), B)));
     if (k != root) root_end = min(uni(root_end), uni(g.info[k].z));
     root_end = uni(root_end);
     int steps = 0;
@@ -517,10 +539,10 @@ __device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int
                             V &visit)
 {
     const int lane = lane_id();
-    const int entry = uni(walk_entry(g, uni(root), B));
-    const int4 ie = g.info[entry];
-    if (!uni_b(node_open(g, entry, B))) return true; // the ball reaches nothing
-    if (lane == 0) la[0] = entry | (int)((uint32_t)(ie.w >> 8) << 31);
+    const int ent = uni(walk_entry(g, uni(root), B));
+    // a node other than the root was entered because the ball reaches it
+    if (item_node(ent) == root && !uni_b(node_open(g, root, B))) return true; // reaches nothing
+    if (lane == 0) la[0] = ent;
     int m = 1;
     wave_lds_sync();
     for (int level = 0; level < 24; level++) {
@@ -531,8 +553,7 @@ __device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int
             const bool vi = idx < m;
             const int it = vi ? la[idx] : 0;
             const bool lf = it < 0;
-            const int node = it & 0x7fffffff;
-            const int cnt = vi ? (lf ? 1 : g.nchild[node]) : 0;
+            const int cnt = vi ? (lf ? 1 : item_kids(it)) : 0;
             int incl = cnt;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -561,19 +582,22 @@ __device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int
                 const bool valid = b0 + lane < total;
                 const int oit = __shfl(it, own, 64);
                 const int slot = b0 + lane - __shfl(pre, own, 64);
-                const int onode = oit & 0x7fffffff;
-                int c = onode, cl = 1;
+                int ci = oit; // a leaf item is carried over
                 bool keep = valid;
-                if (oit >= 0) { // an internal item: test its child `slot`
-                    c = valid ? g.kids[8 * (int64_t)onode + min(max(slot, 0), 7)] : -1;
-                    keep = valid && c >= 0 && node_open(g, c, B);
-                    cl = keep ? (int)(g.info[c].w >> 8) : 1;
+                if (oit >= 0) { // an internal item: test its child `slot` on its record
+                    keep = false;
+                    if (valid) {
+                        const int64_t r = 2 * (8 * (int64_t)item_node(oit) + min(max(slot, 0), 7));
+                        const float4 lo = g.krec[r], hi = g.krec[r + 1];
+                        keep = box_open(lo, hi, B);
+                        ci = __float_as_int(hi.w);
+                    }
                 }
                 const uint64_t km = ballot(keep);
-                if (ballot(keep && !cl)) inner = true;
+                if (ballot(keep && ci >= 0)) inner = true;
                 const int nk = popc64(km);
                 if (mb + nk > LCAP) return false;
-                if (keep) lb[mb + mbcnt(km)] = c | (int)((uint32_t)cl << 31);
+                if (keep) lb[mb + mbcnt(km)] = ci;
                 mb = uni(mb + nk);
             }
         }
@@ -590,7 +614,7 @@ __device__ bool walk_levels(const Geom &g, int root, const Ball &B, int *la, int
         const int idx = c0 + lane;
         const bool vi = idx < m;
         int4 inf = make_int4(0, 0, 0, 0);
-        if (vi) inf = g.info[la[idx] & 0x7fffffff];
+        if (vi) inf = g.info[item_node(la[idx])];
         const uint64_t vl = ballot(vi);
         emit_leaves(vl, inf, visit);
     }
@@ -1330,18 +1354,16 @@ __device__ __forceinline__ void defer_members(uint64_t dm, int a, int32_t *dfr, 
 struct GLds {
     double *cx, *cy, *cz; // [C] staged candidates: raw FP64 positions (NaN past the superset)
     uint64_t *rows;       // [GMR][C / 64]: the masks of member m over the staged chunks
-    double *mh;           // [64] h of member m in the current round
     double *fin;          // [2][64] the lane-reduced sums of member m (W, its h derivative)
-    uint64_t *ctl64;      // [2]: members iterating in the next round, members done
     float *cm;            // [C] staged candidates: m_j
-    int32_t *mcnt;        // [64] neighbour counts of member m in the round
+    int32_t *mcnt;        // [3][64] neighbour counts of member m in round r (row r % 3)
     int32_t *ctl;         // [8]: the group taken
     char *fifo;           // GW FIFOs of 128 * (batches at once) entries
     int C;
 };
 __host__ __device__ constexpr size_t glds_bytes(int C)
 {
-    return (size_t)C * 28 + (size_t)8 * GMR * (C / 64) + 8 * 64 * 3 + 8 * 2 + 64 * 4 + 8 * 4 +
+    return (size_t)C * 28 + (size_t)8 * GMR * (C / 64) + 8 * 64 * 2 + 3 * 64 * 4 + 8 * 4 +
            (size_t)GW * 128 * GFB * 4;
 }
 __device__ __forceinline__ GLds glds_carve(char *p, int C)
@@ -1356,16 +1378,12 @@ __device__ __forceinline__ GLds glds_carve(char *p, int C)
     p += 8 * (size_t)C;
     S.rows = (uint64_t *)p;
     p += (size_t)8 * GMR * (C / 64);
-    S.mh = (double *)p;
-    p += 8 * 64;
     S.fin = (double *)p;
     p += 8 * 128;
-    S.ctl64 = (uint64_t *)p;
-    p += 8 * 2;
     S.cm = (float *)p;
     p += 4 * (size_t)C;
     S.mcnt = (int32_t *)p;
-    p += 64 * 4;
+    p += 3 * 64 * 4;
     S.ctl = (int32_t *)p;
     p += 4 * 8;
     S.fifo = p;
@@ -1383,7 +1401,7 @@ struct GCand {
 // their positions and masses.  The slots past nc up to the end of its chunk
 // get NaN positions, on which every test fails.  Each pass loads GSTG
 // indices per thread, then their records.
-__device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc, const float *__restrict__ m)
+__device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc)
 {
     const int n = min(gc.nc, S.C);
     const int npad = min((gc.nc + 63) & ~63, S.C);
@@ -1396,13 +1414,8 @@ __device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc, cons
             j[u] = t < n ? gc.cg[t] : -1;
         }
         double4 p[GSTG];
-        float mm[GSTG];
 #pragma unroll
-        for (int u = 0; u < GSTG; u++) {
-            const int jj = j[u] < 0 ? 0 : j[u];
-            p[u] = gc.p64[jj];
-            mm[u] = m[jj];
-        }
+        for (int u = 0; u < GSTG; u++) p[u] = gc.p64[j[u] < 0 ? 0 : j[u]];
 #pragma unroll
         for (int u = 0; u < GSTG; u++) {
             const int t = base + u * GW * 64 + (int)threadIdx.x;
@@ -1411,7 +1424,7 @@ __device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc, cons
                 S.cx[t] = v ? p[u].x : nan;
                 S.cy[t] = v ? p[u].y : nan;
                 S.cz[t] = v ? p[u].z : nan;
-                S.cm[t] = v ? mm[u] : 0.0f;
+                S.cm[t] = v ? (float)p[u].w : 0.0f;
             }
         }
     }
@@ -1612,7 +1625,7 @@ struct DensK {
     GroupArg ga;
     CandArg ca;
     const float4 *pos4;  // FP32 x, y, z and m per particle (walks, own-superset count passes)
-    const double4 *p64;  // FP64 x, y, z, h per particle (group filters, pair terms)
+    const double4 *p64;  // FP64 x, y, z and the mass per particle (group staging, pair terms)
     const float *m;
     float *rho, *fgrad;
     sfc_density_out out;
@@ -1677,7 +1690,7 @@ template <int KER, typename ACC> struct DensPair : DensAcc<KER, ACC> {
     __device__ __forceinline__ Term term(const DEnt &e) const
     {
         const double4 pj = p64[e.j];
-        return this->make(pj.x, pj.y, pj.z, m[e.j]);
+        return this->make(pj.x, pj.y, pj.z, (float)pj.w);
     }
 };
 
@@ -1699,7 +1712,7 @@ template <int KER, typename ACC> struct DensPairS : DensAcc<KER, ACC> {
             xj = pj.x;
             yj = pj.y;
             zj = pj.z;
-            mj = m[j];
+            mj = (float)pj.w;
         }
         return this->make(xj, yj, zj, mj);
     }
@@ -1910,14 +1923,15 @@ __device__ __forceinline__ int dens_emit(const DensK &k, const GLds &S, const GC
 } // namespace
 
 // Density, one workgroup per group: the members iterate h together on the
-// staged superset, one filter round at a time.  Wave 0 keeps the members'
-// h loop state in its lanes: after the round's barrier it reads the counts,
-// applies the h step and publishes the new h and the next round's members
-// (a second barrier).  Members whose h outgrows the superset, or whose
-// group kept none, are listed for k_dens_solo with the state they reached;
-// every member that finished is then streamed by one wave into its sums from
-// its masks of the last round, and wave 0 finishes rho, drho/dh and f of
-// all of them, one lane each.
+// staged superset, one filter round at a time.  Every wave keeps the h loop
+// state of all members in its lanes (lane m: member m) and applies the same
+// h step after the round's barrier, so one barrier per round suffices (the
+// counts of round r go to row r % 3 of S.mcnt; wave 0 clears row r + 1 in
+// round r, when every wave has read it in round r - 2).  Members whose h
+// outgrows the superset, or whose group kept none, are listed for
+// k_dens_solo with the state they reached; every member that finished is
+// then streamed by one wave into its sums from its masks of the last round,
+// and wave 0 finishes rho, drho/dh and f of all of them, one lane each.
 template <int KER, typename ACC>
 __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_dgrp(DensK k)
 {
@@ -1940,54 +1954,49 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
         const bool wrap = (s.flags & GSUP_WRAP) || k.drift;
         const GCand gc{k.ca.cand + s.c0, s.nc, k.p64};
         GMem gm = grp_members(k.g, k.ga, k.active, a0, M, s, bx.L, dl);
-        // wave 0: the h loop state of member `lane`
+        // the h loop state of member `lane` (the same in every wave)
         int it = 0, nn = 0;
         int stt = gm.live ? ((s.flags & GSUP_SOLO) ? ST_DEFER : ST_ITER) : ST_DONE;
         if (stt == ST_ITER && !(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
         double lo = 0.0, hi = INFINITY;
         bool conv = false;
-        uint64_t ev = ballot(stt == ST_ITER); // the same in every wave at the start
+        uint64_t ev = ballot(stt == ST_ITER);
         if (wv == 0) {
             S.mcnt[lane] = 0;
-            S.mh[lane] = gm.h;
+            S.mcnt[64 + lane] = 0;
         }
-        if (!(s.flags & GSUP_SOLO)) stage_cands(S, gc, k.m);
+        if (!(s.flags & GSUP_SOLO)) stage_cands(S, gc);
         __syncthreads();
         for (int round = 0; ev && round <= k.max_iter; round++) {
+            int32_t *cnt = S.mcnt + 64 * (round % 3);
+            if (wv == 0) S.mcnt[64 * ((round + 1) % 3) + lane] = 0;
             if (wrap)
-                grp_round<true>(S, gc, s, bx.L, ev, gm, S.mcnt);
+                grp_round<true>(S, gc, s, bx.L, ev, gm, cnt);
             else
-                grp_round<false>(S, gc, s, bx.L, ev, gm, S.mcnt);
+                grp_round<false>(S, gc, s, bx.L, ev, gm, cnt);
             __syncthreads();
-            if (wv == 0) {
-                ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)s.nc;
-                if ((ev >> lane) & 1ull) {
-                    it++;
-                    nn = S.mcnt[lane];
-                    S.mcnt[lane] = 0;
-                    if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
-                        conv = true;
-                        stt = ST_DONE;
-                    } else if (it >= k.max_iter) {
-                        stt = ST_DONE;
-                    } else {
-                        gm.h = h_step(nn, k.n_ngb, k.dn, gm.h, lo, hi);
-                        S.mh[lane] = gm.h;
-                        if (!(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
-                    }
+            if (wv == 0) ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)s.nc;
+            if ((ev >> lane) & 1ull) {
+                it++;
+                nn = cnt[lane];
+                if (k.fixed_h || (nn >= k.n_ngb - k.dn && nn <= k.n_ngb + k.dn)) {
+                    conv = true;
+                    stt = ST_DONE;
+                } else if (it >= k.max_iter) {
+                    stt = ST_DONE;
+                } else {
+                    gm.h = h_step(nn, k.n_ngb, k.dn, gm.h, lo, hi);
+                    if (!(gm.h + gm.d <= s.cov)) stt = ST_DEFER;
                 }
-                const uint64_t nx = ballot(stt == ST_ITER);
-                if (lane == 0) S.ctl64[0] = nx;
             }
-            __syncthreads();
-            ev = uni_u64(S.ctl64[0]);
-            if (wv != 0) gm.h = S.mh[lane];
+            ev = ballot(stt == ST_ITER);
         }
+        const bool done = gm.live && stt == ST_DONE;
+        const uint64_t dn = ballot(done);
         if (wv == 0) {
             // a member still iterating here has hit the round limit: impossible
             // while every round advances it, kept as a guard
             if (ballot(stt == ST_ITER)) guard_hit(k.st);
-            const bool done = gm.live && stt == ST_DONE;
             const uint64_t dm = ballot(gm.live && stt == ST_DEFER);
             if ((dm >> lane) & 1ull) k.dstate[a0 + lane] = make_double4(gm.h, lo, hi, (double)it);
             defer_members(dm, a0 + lane, k.dfr, k.st);
@@ -2000,12 +2009,9 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
             }
             ws.iters += (uint32_t)uni(wave_sum_i(done ? it : 0));
             ws.not_conv += (uint32_t)popc64(ballot(done && !conv));
-            const uint64_t dn = ballot(done);
-            if (lane == 0) S.ctl64[1] = dn;
         }
-        __syncthreads();
-        // the r-th member that finished is streamed by wave r mod GW
-        const uint64_t dn = uni_u64(S.ctl64[1]);
+        // the r-th member that finished is streamed by wave r mod GW (the
+        // masks and the staged superset are complete since the last barrier)
         uint64_t rest = dn;
         for (int r = 0; rest; r++) {
             const int m = ctz64(rest);
@@ -2016,7 +2022,7 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
             ws.pairs += (unsigned long long)c;
         }
         __syncthreads();
-        if (wv == 0 && ((dn >> lane) & 1ull)) dens_finish<KER>(k, gm.i, gm.h, S.fin[lane], S.fin[64 + lane]);
+        if (wv == 0 && done) dens_finish<KER>(k, gm.i, gm.h, S.fin[lane], S.fin[64 + lane]);
     }
     ws.flush(k.st);
 }
@@ -2025,7 +2031,8 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 // (radius: the bracket's upper end, or 1.25 h while there is none), walked
 // up to three times, and the h loop continued on it from where the group
 // left it; only when that fails too does it walk once per h evaluation.
-template <int KER, typename ACC> __global__ __launch_bounds__(256) void k_dens_solo(DensK k)
+template <int KER, typename ACC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_dens_solo(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const MemLds S = mem_carve(lds_raw, k.ga.T, true);
@@ -2069,8 +2076,8 @@ struct HydroK {
     const float *m, *vx, *vy, *vz, *u, *rho, *fgrad;
     const float4 *pa;   // per particle: m, vx, vy, vz
     const float4 *pb;   // per particle: rho, f P / rho^2, sound speed, h
-    const float4 *pos4; // per particle: FP32 x, y, z, h (walks)
-    const double4 *p64; // per particle: FP64 x, y, z, h (group filters, pair terms)
+    const float4 *pos4; // per particle: FP32 x, y, z, h (walks, the filter's screen)
+    const double4 *p64; // per particle: FP64 x, y, z, h (pair terms)
     const unsigned long long *drift; // reused supersets: largest displacement, h growth, or NULL
     const uint8_t *active;           // reused supersets: the members computed now
     int32_t *dfr;                    // members that walk alone (st->n_dfr of them)
@@ -2309,7 +2316,7 @@ __global__ void k_dens_prep(int64_t n, const double *__restrict__ x, const doubl
     if (i >= n) return;
     const double xi = x[i], yi = y[i], zi = z[i];
     pos4[i] = make_float4((float)xi, (float)yi, (float)zi, m[i]);
-    p64[i] = make_double4(xi, yi, zi, h[i]);
+    p64[i] = make_double4(xi, yi, zi, (double)m[i]); // the mass in one block with x
     if (snap) snap[i] = make_double4(xi, yi, zi, 0.0);
 }
 
@@ -2676,6 +2683,7 @@ Geom make_geom(const PartDev &p, const TreeDev &t)
     g.lo = t.lo;
     g.hi = t.hi;
     g.box32 = t.box32;
+    g.krec = t.krec;
     g.kids = t.kids;
     g.nchild = t.nchild;
     g.box_root = t.box_root;

@@ -301,6 +301,29 @@ __global__ void k_tree_up3(const TreeDev t, const DevStatus *st_in, int with_bbo
     }
 }
 
+// The child records of every node (after its children's boxes are final):
+// slot s of node p gets child s's outward-rounded FP32 box and its item, so
+// that a walk tests all children of a node with one load per child.
+__global__ void k_tree_krec(const TreeDev t, const DevStatus *st)
+{
+    const int nn = min(st->n_nodes, t.capacity);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < 8 * (int64_t)nn; q += stride) {
+        const int c = t.kids[q];
+        float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+        float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, __int_as_float(-1));
+        if (c >= 0 && c < nn) {
+            const int leaf = t.info[c].w >> 8;
+            const int nc = t.nchild[c];
+            lo = t.box32[2 * (int64_t)c];
+            hi = t.box32[2 * (int64_t)c + 1];
+            hi.w = __int_as_float(leaf ? (c | (int)0x80000000u) : (c | ((max(nc, 1) - 1) << 28)));
+        }
+        t.krec[2 * q] = lo;
+        t.krec[2 * q + 1] = hi;
+    }
+}
+
 hipError_t launch_tree_build(hipStream_t s, const PartDev &p, const uint64_t *keys, int n_leaf,
                              TreeBufs &tb, TreeDev &t, uint32_t *scan_tmp, DevStatus *st)
 {
@@ -344,5 +367,7 @@ hipError_t launch_tree_refit(hipStream_t s, const PartDev &p, TreeDev &t, bool b
         k_tree_up3<<<gnodes, 256, 0, s>>>(t, st, bbox ? 1 : 0, level);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    return hipSuccess;
+    const int64_t gk = (8 * (int64_t)t.capacity + 255) / 256;
+    k_tree_krec<<<(unsigned)(gk < 4096 ? gk : 4096), 256, 0, s>>>(t, st);
+    return hipGetLastError();
 }
