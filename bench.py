@@ -242,6 +242,15 @@ def main():
     pl.ctx.status_clear()
     pl.hydro_force()
     st_h = pl.ctx.status()
+    # the schedule of one traced step (untimed): how long the device runs
+    # for the slowest workgroup / wave after the average one is done
+    pl.ctx.set_trace(True)
+    pl.step()
+    st_tr = pl.ctx.status()
+    pl.ctx.set_trace(False)
+    sched = {name: {"units": st_tr["sched_units"][k], "span_us": round(st_tr["sched_span_us"][k], 1),
+                    "tail_us": round(st_tr["sched_tail_us"][k], 1)}
+             for k, name in enumerate(("k_dgrp_workgroups", "k_hmem_waves"))}
 
     speed = None
     if not args.no_ungrouped:
@@ -353,6 +362,7 @@ def main():
         "cand_per_active_hydro": round(st_h["sum_cand"] / A, 1),
         "h_evaluations_per_active": round(st_d["sum_iters"] / A, 3),
         "solo_members": st_d["n_deferred"] + st_h["n_deferred"],
+        "schedule": sched,
         "roofline": roof,
         "error_vs_fp64_oracle": err,
         "cpu_baseline": cpu,

@@ -59,6 +59,12 @@ typedef struct sfc_ctx sfc_ctx;
 SFC_API int sfc_ctx_create(sfc_ctx **out, void *hip_stream);
 SFC_API void sfc_ctx_destroy(sfc_ctx *ctx);
 SFC_API int sfc_ctx_set_stream(sfc_ctx *ctx, void *hip_stream);
+/* Schedule statistics (sfc_status.sched_*): on = 1 makes every workgroup of
+ * the density group kernel and every wave of the hydro member kernel record
+ * its start and end on the device's constant clock (four atomics each, into
+ * one of eight per-XCD slots of the status block); on = 0 (the default)
+ * records nothing.  SFC_EINVAL for other values. */
+SFC_API int sfc_ctx_set_trace(sfc_ctx *ctx, int on);
 /* Message of the last host-detected error (static storage of the context). */
 SFC_API const char *sfc_ctx_last_error(const sfc_ctx *ctx);
 /* Number of compute units of the context's device. */
@@ -173,6 +179,10 @@ typedef struct {
                             Recycling": groups as the leaves inside nodes of one tree depth).
                             Node = Hilbert cell of the last tree_build, so the tree and its
                             n_leaf decide the leaves. */
+    int32_t t_cand;      /* in a per-box table only: the most candidates a group superset of
+                            this box may hold in the density and hydro calls that follow
+                            (0 = the call's t_cand; else clamped to [64, the call's t_cand]);
+                            a group whose superset exceeds it finishes member by member */
 } sfc_group_params;
 
 /* Optional neighbour-set dump (testing): for every active particle i,
@@ -350,6 +360,16 @@ typedef struct {
     int64_t sum_iters;       /* h evaluations (since bind) */
     int64_t sum_tests;       /* member x superset-candidate tests of the filters (since bind) */
     int64_t sum_pairs;       /* neighbour pairs summed by density and hydro (since bind) */
+    /* With sfc_ctx_set_trace(ctx, 1): the schedule of the last density pass
+     * [0] and the last hydro pass [1] (device's constant clock; zero while
+     * tracing is off): the workgroups of the density group
+     * kernel, resp. the waves of the hydro member kernel, that ran, the time
+     * from the first one's start to the last one's end, and the tail: the
+     * last end minus the mean end (how long the device ran for its slowest
+     * unit after the average one had finished). */
+    int64_t sched_units[2];
+    double sched_span_us[2];
+    double sched_tail_us[2];
 } sfc_status;
 
 /* Synchronise the stream and copy the status block to *out.  Returns

@@ -37,7 +37,7 @@ from .pipeline import Pipeline, StepConfig
 
 F_GRID = (0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0)
 NG_GRID = (4, 8, 16, 24, 32, 48, 64)
-T_GRID = (1024, 2048, 4096)
+T_GRID = (256, 512, 1024, 2048, 4096)
 LEAF_GRID = (8, 16, 32, 64, 128, 256)
 SKIN_GRID = (1.0, 1.05, 1.1)
 LEVEL_GRID = (3, 4, 5, 6, 7, 8)  # tree policy: depth of the grouping nodes
@@ -193,14 +193,17 @@ def tuned_config(w, retune=False, log=print, path=None, measure_fn=None) -> Step
 
 def per_box_params(w, cfg_for_box) -> np.ndarray:
     """Per-box group parameter table (device layout of sfc_group_params) for a
-    batch of boxes: cfg_for_box(b, n_b, active_fraction) -> (policy, cap, f[, level])."""
+    batch of boxes: cfg_for_box(b, n_b, active_fraction) -> (policy, cap, f[, level
+    [, t_cand]]) (t_cand 0: the call's)."""
     nb = len(w.box_L)
     arr = (S.GroupParams * nb)()
     for b in range(nb):
         a0, a1 = int(w.box_off[b]), int(w.box_off[b + 1])
         frac = float(w.state["active"][a0:a1].mean()) if a1 > a0 else 0.0
-        pol, cap, f, *lev = cfg_for_box(b, a1 - a0, frac)
-        arr[b] = S.GroupParams(int(pol), int(cap), float(f), int(lev[0]) if lev else 0)
+        pol, cap, f, *rest = cfg_for_box(b, a1 - a0, frac)
+        lev = int(rest[0]) if len(rest) > 0 else 0
+        tc = int(rest[1]) if len(rest) > 1 else 0
+        arr[b] = S.GroupParams(int(pol), int(cap), float(f), lev, tc)
     return np.frombuffer(bytes(arr), dtype=np.uint8).copy()
 
 
@@ -232,9 +235,10 @@ def box_buckets(w) -> dict:
 
 def tune_boxes(w, base: StepConfig, log=print, rounds=1, measure_fn=None):
     """Per-box group parameters for a batch: each bucket's largest box tuned
-    on its own over the group policy/f and the cap (launch-wide parameters
-    from `base`).  Returns (cfg_for_box for per_box_params, per-bucket
-    results)."""
+    on its own over the group policy/f, the cap and the superset tile
+    (launch-wide parameters from `base`; a bucket's tile becomes its boxes'
+    t_cand, under the launch's).  Returns (cfg_for_box for per_box_params,
+    per-bucket results)."""
     res = {}
     for sig, boxes in sorted(box_buckets(w).items()):
         rep = max(boxes, key=lambda b: int(w.box_off[b + 1] - w.box_off[b]))
@@ -242,8 +246,8 @@ def tune_boxes(w, base: StepConfig, log=print, rounds=1, measure_fn=None):
         log(f"bucket {sig}: {len(boxes)} boxes, tuning box {rep} ({sw.n} particles, "
             f"{sw.n_active} active)")
         best, c, _ = tune(sw, base, rounds=rounds, log=log, measure_fn=measure_fn,
-                          axes=("group", "cap"))
-        res[sig] = (best.policy, best.n_group_max, best.f, best.level)
+                          axes=("group", "cap", "tile"))
+        res[sig] = (best.policy, best.n_group_max, best.f, best.level, best.t_cand)
 
     def cfg_for_box(b, n_b, frac):
         if n_b == 0 or frac <= 0:

@@ -52,6 +52,8 @@ struct sfc_ctx {
     hipStream_t stream;
     int device;
     int cu;
+    int wclk_khz; // the device's constant clock (wall_clock64), kHz
+    bool trace;   // schedule statistics of the group and member kernels
     char err[512];
     bool bound;
     sfc_dims dims;
@@ -192,6 +194,7 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     gb.goff = b.take<int32_t>(n + 1);
     gb.n_act = b.take<int32_t>(1);
     gb.n_groups = b.take<int32_t>(1);
+    gb.box_T = b.take<int32_t>(nb);
     SearchBufs xb;
     xb.cand_cap = cand_capacity(d);
     xb.cand = b.take<int32_t>(xb.cand_cap);
@@ -298,6 +301,7 @@ int sfc_ctx_create(sfc_ctx **out, void *hip_stream)
     c->stream = (hipStream_t)hip_stream;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->wclk_khz, hipDeviceAttributeWallClockRate, c->device);
     if (e != hipSuccess) {
         delete c;
         return SFC_EHIP;
@@ -310,6 +314,13 @@ int sfc_ctx_create(sfc_ctx **out, void *hip_stream)
 }
 
 void sfc_ctx_destroy(sfc_ctx *ctx) { delete ctx; }
+
+int sfc_ctx_set_trace(sfc_ctx *ctx, int on)
+{
+    if (!ctx || (on != 0 && on != 1)) return SFC_EINVAL;
+    ctx->trace = on != 0;
+    return SFC_OK;
+}
 
 int sfc_ctx_set_stream(sfc_ctx *ctx, void *hip_stream)
 {
@@ -560,6 +571,7 @@ int density(sfc_ctx *ctx, sfc_particles *p, const sfc_density_params *dp, sfc_de
     DensityArgs a;
     a.dp = *dp;
     a.keep = ctx->dims.keep_supersets && !dp->reuse;
+    a.trace = ctx->trace;
     if (out) a.out = *out;
     else memset(&a.out, 0, sizeof(a.out));
     PartDev pd = part_dev(p);
@@ -615,6 +627,7 @@ int hydro_force(sfc_ctx *ctx, const sfc_particles *p, const sfc_hydro_params *hp
     a.hp = *hp;
     a.out = *out;
     a.keep = ctx->dims.keep_supersets && !hp->reuse;
+    a.trace = ctx->trace;
     PartDev pd = part_dev(p);
     // the hydro walks read every node's max h: refresh it from the current h
     // (and the boxes after a drift, for the members that walk alone)
@@ -647,6 +660,24 @@ int sfc_status_read(sfc_ctx *ctx, sfc_status *out)
     out->sum_iters = (int64_t)s.sum_iters;
     out->sum_tests = (int64_t)s.sum_tests;
     out->sum_pairs = (int64_t)s.sum_pairs;
+    for (int k = 0; k < 2; k++) {
+        // the eight per-XCD slots combined
+        unsigned long long t0 = ~0ull, t1 = 0, n = 0;
+        double sum = 0.0;
+        for (int x = 0; x < 8; x++) {
+            const unsigned long long *q = s.sched[k][x];
+            if (!q[3]) continue;
+            t0 = q[0] < t0 ? q[0] : t0;
+            t1 = q[1] > t1 ? q[1] : t1;
+            sum += (double)q[2];
+            n += q[3];
+        }
+        const bool ok = n > 0 && t1 >= t0 && ctx->wclk_khz > 0;
+        const double us = ok ? 1000.0 / (double)ctx->wclk_khz : 0.0; // microseconds per tick
+        out->sched_units[k] = ok ? (int64_t)n : 0;
+        out->sched_span_us[k] = ok ? (double)(t1 - t0) * us : 0.0;
+        out->sched_tail_us[k] = ok ? ((double)t1 - sum / (double)n) * us : 0.0;
+    }
     if (s.flags & (SFC_ST_LIST_OVERFLOW | SFC_ST_NODE_OVERFLOW | SFC_ST_GUARD))
         return fail(ctx, SFC_EOVERFLOW, "device capacity or loop limit exceeded (flags 0x%x)", s.flags);
     return SFC_OK;

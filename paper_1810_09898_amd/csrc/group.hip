@@ -268,6 +268,13 @@ int group_levels(int64_t n, int64_t *n_items, int64_t *span)
     return L;
 }
 
+// the per-box superset caps of a per-box table (0 without one)
+__global__ void k_box_tiles(const sfc_group_params *gp_box, int nb, int32_t *box_T)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) box_T[b] = gp_box ? gp_box[b].t_cand : 0;
+}
+
 hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params *gp,
                          const sfc_group_params *gp_box, const int8_t *dlev, GroupBufs &g,
                          uint32_t *scan_tmp, DevStatus *st)
@@ -292,7 +299,7 @@ hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params
     c.act = g.act;
     c.n_act = g.n_act;
     if (gp) c.gp = *gp;
-    else c.gp = sfc_group_params{SFC_POLICY_COUNT, 1, 0.0, 0};
+    else c.gp = sfc_group_params{SFC_POLICY_COUNT, 1, 0.0, 0, 0};
     c.gp_box = gp_box;
     c.dlev = dlev;
     k_group_next<<<(unsigned)((n + NX_THREADS - 1) / NX_THREADS), NX_THREADS, 0, s>>>(c, g.nxt);
@@ -316,5 +323,7 @@ hipError_t launch_groups(hipStream_t s, const PartDev &p, const sfc_group_params
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     k_group_emit<<<(unsigned)ni[0], 64, 0, s>>>(g.n_act, g.nxt, g.ent[0], g.before[0], g.goff);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_box_tiles<<<(unsigned)((p.nb + 255) / 256), 256, 0, s>>>(gp_box, p.nb, g.box_T);
     return hipGetLastError();
 }

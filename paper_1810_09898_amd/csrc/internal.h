@@ -137,6 +137,12 @@ struct DevStatus {
     unsigned long long sum_tests;
     unsigned long long sum_pairs;
     unsigned long long n_dfr; // per pass: hydro members deferred to their own walks
+    // with tracing on, per pass, for the density group kernel [0] and the
+    // hydro member kernel [1], per XCD (each on a 128-byte line of its own):
+    // the earliest start and the latest end of a workgroup (density) or wave
+    // (hydro) on the device's constant clock, the sum of their end times and
+    // their number
+    unsigned long long sched[2][8][16];
     // Per-pass counters of the search kernels, one per eighth of the work
     // items, each on its own 128-byte line so that the eighths do not
     // serialise on one address: bump pointers of the eight regions of the
@@ -257,6 +263,7 @@ struct GroupBufs {
     int32_t *ent[GROUP_LEVELS_MAX];
     int32_t *before[GROUP_LEVELS_MAX];
     int32_t *goff;       // [n+1]
+    int32_t *box_T;      // [n_boxes] per-box superset cap of the last grouping (0: the call's)
     int32_t *n_act;      // device scalar
     int32_t *n_groups;   // device scalar
 };
@@ -291,11 +298,13 @@ struct DensityArgs {
     sfc_density_params dp;
     sfc_density_out out;
     bool keep; // snapshot x, y, z for a later reuse
+    bool trace; // schedule statistics
 };
 struct HydroArgs {
     sfc_hydro_params hp;
     sfc_hydro_out out;
     bool keep; // snapshot x, y, z, h for a later reuse
+    bool trace; // schedule statistics
 };
 hipError_t launch_density(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
                           SearchBufs &sb, const DensityArgs &a, DevStatus *st);

@@ -232,6 +232,7 @@ struct Geom {
 };
 struct GroupArg {
     const int32_t *act, *goff, *n_groups, *n_act;
+    const int32_t *box_T; // per-box superset caps (0: T)
     int T;
 };
 struct CandArg {
@@ -787,6 +788,7 @@ __device__ __forceinline__ bool pair_wrap(bool folded, double cand_ext_lane, boo
 struct BoxInfo {
     double L;
     int root, root_end;
+    int b;
 };
 __device__ __forceinline__ BoxInfo box_info(const Geom &geo, int i)
 {
@@ -795,6 +797,7 @@ __device__ __forceinline__ BoxInfo box_info(const Geom &geo, int i)
     bi.L = uni_d(geo.box_L[b]);
     bi.root = uni(geo.box_root[b]);
     bi.root_end = uni(geo.box_root[b + 1]);
+    bi.b = b;
     return bi;
 }
 
@@ -813,10 +816,11 @@ struct WalkK {
 
 // per-pass reset of the candidate buffer and the work counters (a kernel,
 // not a memset, so that the step can be captured in a graph)
-__global__ void k_reset_pass(DevStatus *st)
+__global__ void k_reset_pass(DevStatus *st, int pass)
 {
     const int t = threadIdx.x;
     if (blockIdx.x != 0) return;
+    if (t < 32) st->sched[pass][t >> 2][t & 3] = (t & 3) == 0 ? ~0ull : 0ull;
     if (t < 8) {
         st->cand_top[16 * t] = 0ull;
         st->qctr[32 * t] = 0;
@@ -940,8 +944,11 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
         if (!walked) { // the buffer is used up: the members walk on their own
             flags = GSUP_SOLO;
         } else {
-            AppendCand ap(k.pos4, k.ca.cand + ck.cur, T, B, nowrap ? rad : 0.0,
-                          (int)min((int64_t)T, ck.end - ck.cur), &ck);
+            // the box's own cap on the superset, if its grouping table set one
+            const int tb = k.ga.box_T ? uni(k.ga.box_T[bx.b]) : 0;
+            const int Tb = tb > 0 ? min(max(tb, 64), T) : T;
+            AppendCand ap(k.pos4, k.ca.cand + ck.cur, Tb, B, nowrap ? rad : 0.0,
+                          (int)min((int64_t)Tb, ck.end - ck.cur), &ck);
             if (!walk_levels(k.g, bx.root, B, lst, lst + LCAP, lst + 2 * LCAP, ap)) // list too long: window walk
                 walk(k.g, bx.root, bx.root_end, B, ap, k.st);
             nc = uni(ap.n);
@@ -1607,6 +1614,19 @@ __device__ __forceinline__ void grp_round(const GLds &S, const GCand &gc, const 
     if ((ev >> lane) & 1ull) atomicAdd(&cnt_m[lane], cntv);
 }
 
+// the start and end of one workgroup or wave of a scheduled kernel (slot k
+// of DevStatus::sched), on the device's constant clock: the spread of the
+// ends is the tail that the work queues leave
+__device__ __forceinline__ void sched_mark(DevStatus *st, int k, unsigned long long t0)
+{
+    const unsigned long long t1 = wall_clock64();
+    unsigned long long *q = st->sched[k][blockIdx.x & 7];
+    atomicMin(&q[0], t0);
+    atomicMax(&q[1], t1);
+    atomicAdd(&q[2], t1);
+    atomicAdd(&q[3], 1ull);
+}
+
 // the group taken by the workgroup (wave 0 takes it; -1: none left)
 __device__ __forceinline__ int wg_take(Queue &q, const GLds &S)
 {
@@ -1637,6 +1657,7 @@ struct DensK {
     double4 *dstate;                 // per active: h, bracket lo, hi and evaluations so far
     int n_ngb, dn, max_iter, fixed_h;
     int C;                           // candidates a group workgroup stages in LDS
+    int trace; // schedule statistics (DevStatus::sched)
 };
 
 namespace {
@@ -1936,6 +1957,7 @@ template <int KER, typename ACC>
 __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_dgrp(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
+    const unsigned long long t_start = wall_clock64();
     const GLds S = glds_carve(lds_raw, k.C);
     const int lane = lane_id();
     const int wv = uni((int)(threadIdx.x >> 6));
@@ -2025,6 +2047,7 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
         if (wv == 0 && done) dens_finish<KER>(k, gm.i, gm.h, S.fin[lane], S.fin[64 + lane]);
     }
     ws.flush(k.st);
+    if (k.trace && threadIdx.x == 0) sched_mark(k.st, 0, t_start);
 }
 
 // One wave per member that left its group superset: a superset of its own
@@ -2088,6 +2111,7 @@ struct HydroK {
     const float4 *pc;
     const float *alpha_i;
     double alpha_u, alpha_min, alpha_max, ell;
+    int trace; // schedule statistics (DevStatus::sched)
 };
 
 namespace {
@@ -2431,6 +2455,7 @@ template <int KER, typename ACC, int PHYS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? (PHYS ? 4 : 5) : 1))) void k_hmem(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
+    const unsigned long long t_start = wall_clock64();
     HEnt *fifo = (HEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
     const int lane = lane_id();
     const int A = uni(*k.ga.n_act);
@@ -2503,6 +2528,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
         hydro_write<KER, ACC>(k, M.i, hp);
     }
     ws.flush(k.st);
+    if (k.trace && lane == 0) sched_mark(k.st, 1, t_start);
 }
 
 // The hydro members that their group's superset does not cover (their group
@@ -2698,6 +2724,7 @@ GroupArg make_groups(const GroupBufs &gb, int T)
     a.goff = gb.goff;
     a.n_groups = gb.n_groups;
     a.n_act = gb.n_act;
+    a.box_T = gb.box_T;
     a.T = T;
     return a;
 }
@@ -2750,7 +2777,7 @@ constexpr int MEM_WAVES = 4; // member waves per workgroup of the solo kernels
 hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const GroupBufs &g,
                        SearchBufs &sb, DevStatus *st, int T, double skin, int hydro)
 {
-    k_reset_pass<<<1, 64, 0, s>>>(st);
+    k_reset_pass<<<1, 64, 0, s>>>(st, hydro);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     WalkK k;
@@ -2822,7 +2849,7 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (dp.reuse) {
         // the kept supersets: the walk is skipped, the drift bounds them
-        k_reset_pass<<<1, 64, 0, s>>>(st);
+        k_reset_pass<<<1, 64, 0, s>>>(st, 0);
         e = launch_drift(s, p, nullptr, g, sb);
     } else {
         e = launch_walk(s, p, t, g, gs, st, T, dp.skin, 0);
@@ -2845,6 +2872,7 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.dn = dp.dn;
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
+    k.trace = a.trace ? 1 : 0;
     k.C = T < GC_MAX ? T : GC_MAX;
     k.drift = dp.reuse ? sb.drift : nullptr;
     k.active = dp.reuse ? p.active : nullptr;
@@ -2898,7 +2926,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (hp.reuse) {
-        k_reset_pass<<<1, 64, 0, s>>>(st);
+        k_reset_pass<<<1, 64, 0, s>>>(st, 1);
         e = launch_drift(s, p, p.h, g, sb);
     } else {
         e = launch_walk(s, p, t, g, sb, st, hp.t_cand, hp.skin, 1);
@@ -2924,6 +2952,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.st = st;
     k.gamma = hp.gamma;
     k.alpha = hp.alpha;
+    k.trace = a.trace ? 1 : 0;
     k.pc = sb.pc;
     k.alpha_i = hp.alpha_i;
     k.alpha_u = hp.alpha_u;

@@ -117,8 +117,10 @@ def run(w, cfg, label, steps, gp_box=None, graph=False, precision=False):
     pl.step()
     torch.cuda.synchronize()
     pl.ctx.status_clear()
+    pl.ctx.set_trace(True)  # the schedule's tail, on this one step only
     pl.step()
     st = pl.ctx.status(raise_on_overflow=False)
+    pl.ctx.set_trace(False)
     ph = _phases(pl, steps)
     A = int(w.state["active"].sum())
     t = sum(ph.values())
@@ -311,6 +313,9 @@ def main():
                     help="skin: finer bins of lognormal_bins on the full step's supersets")
     ap.add_argument("--sweep", action="store_true",
                     help="plummer_clustered: the N_group sweep {1, 8, 16, 32, 64}")
+    ap.add_argument("--tune-boxes", action="store_true",
+                    help="plummer_batch: also tune the per-box group parameters (graph replays of "
+                         "each size/activity bucket's largest box) and time the batch with them")
     args = ap.parse_args()
     from . import workloads as W
     from . import autotune
@@ -332,8 +337,17 @@ def main():
                    [float(v) for v in args.fracs.split(",")])
     elif args.workload == "plummer_batch":
         cfg = StepConfig(n_leaf=16, n_group_max=32, f=0.5, t_cand=1024, hydro_t_cand=1024)
-        run(w, cfg, "plummer_batch (per-box parameters)", args.steps,
+        run(w, cfg, "plummer_batch (hand rule per box)", args.steps,
             gp_box=autotune.per_box_params(w, autotune.batch_rule))
+        if args.tune_boxes:
+            t1 = time.time()
+            cfg_for_box, res = autotune.tune_boxes(
+                w, cfg, log=lambda m: print(f"# {m}", file=sys.stderr, flush=True))
+            print(json.dumps({"workload": "plummer_batch", "kind": "per-box tuning",
+                              "seconds": round(time.time() - t1, 1),
+                              "buckets": {str(k): v for k, v in res.items()}}), flush=True)
+            run(w, cfg, "plummer_batch (tuned per box)", args.steps,
+                gp_box=autotune.per_box_params(w, cfg_for_box))
     elif args.workload == "lognormal_bins":
         base = dict(w.state)
         for b, frac in ((0, "100%"), (1, "10%"), (2, "1%")):

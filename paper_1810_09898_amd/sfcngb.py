@@ -25,7 +25,8 @@ SORT_STATIC_MAX_N = 262144
 ST_LIST_OVERFLOW, ST_NODE_OVERFLOW, ST_BAD_INPUT, ST_GUARD, ST_REUSE_ACTIVE = 1, 2, 4, 8, 16
 
 EXPORTS = [
-    "sfc_ctx_create", "sfc_ctx_destroy", "sfc_ctx_set_stream", "sfc_ctx_last_error",
+    "sfc_ctx_create", "sfc_ctx_destroy", "sfc_ctx_set_stream", "sfc_ctx_set_trace",
+    "sfc_ctx_last_error",
     "sfc_ctx_cu_count", "sfc_workspace_bytes", "sfc_workspace_bind", "sfc_sort",
     "sfc_sort_static", "tree_build",
     "tree_refit_hmax", "tree_refit", "group_ngb_search", "density", "hydro_force", "sfc_status_read",
@@ -57,7 +58,7 @@ class CParticles(C.Structure):
 
 class GroupParams(C.Structure):
     _fields_ = [("policy", C.c_int32), ("n_group_max", C.c_int32), ("f", C.c_double),
-                ("level", C.c_int32)]
+                ("level", C.c_int32), ("t_cand", C.c_int32)]
 
 
 class Verify(C.Structure):
@@ -100,10 +101,12 @@ class Status(C.Structure):
                 ("n_groups", C.c_int32), ("n_deferred", C.c_int64), ("n_overflow", C.c_int64),
                 ("n_not_converged", C.c_int64), ("sum_cand", C.c_int64),
                 ("n_walks", C.c_int64), ("sum_iters", C.c_int64), ("sum_tests", C.c_int64),
-                ("sum_pairs", C.c_int64)]
+                ("sum_pairs", C.c_int64), ("sched_units", C.c_int64 * 2),
+                ("sched_span_us", C.c_double * 2), ("sched_tail_us", C.c_double * 2)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: (list(getattr(self, k)) if k.startswith("sched") else getattr(self, k))
+                for k, _ in self._fields_}
 
 
 class Views(C.Structure):
@@ -131,6 +134,8 @@ def load_library(path: str = LIB_PATH):
     L.sfc_ctx_destroy.restype = None
     L.sfc_ctx_set_stream.argtypes = [_P, _P]
     L.sfc_ctx_set_stream.restype = I
+    L.sfc_ctx_set_trace.argtypes = [_P, I]
+    L.sfc_ctx_set_trace.restype = I
     L.sfc_ctx_last_error.argtypes = [_P]
     L.sfc_ctx_last_error.restype = C.c_char_p
     L.sfc_ctx_cu_count.argtypes = [_P]
@@ -336,6 +341,11 @@ class Context:
 
     def status_clear(self):
         self._check(self.L.sfc_status_clear(self.h))
+
+    def set_trace(self, on: bool):
+        """Schedule statistics of the group and member kernels (status()'s
+        sched_* fields); off by default."""
+        self._check(self.L.sfc_ctx_set_trace(self.h, 1 if on else 0))
 
     def views(self) -> Views:
         v = Views()

@@ -122,6 +122,7 @@ def test_per_box_tuning_and_table():
         rep_act = int(w.state["active"][w.box_off[rep]:w.box_off[rep + 1]].sum())
         assert arr[b].n_group_max == (32 if rep_act > 3000 else 8)
         assert arr[b].policy == S.POLICY_PAPER and arr[b].f == 0.5
+        assert arr[b].t_cand == AT.prior(w).t_cand  # the stand-in cost ignores the tile
     # the sub-workload of a box is that box alone
     sw = AT.sub_workload(w, 2)
     assert sw.n == int(w.box_off[3] - w.box_off[2])

@@ -648,3 +648,32 @@ def test_host_side_errors(plum_small):
     assert e.value.code == S.SFC_EINVAL
     with pytest.raises(S.SfcError):
         pl.ctx.tree_build(pl.ps, pl.keys, 0)
+
+
+def test_per_box_superset_caps(batch):
+    """Per-box superset caps (sfc_group_params.t_cand in a per-box table):
+    boxes capped at 64 candidates send their groups' members to their own
+    walks, which the overflow count shows, and every output is the same bits
+    as without the caps (the sums do not depend on the superset)."""
+    import torch
+    nb = len(batch.box_L)
+
+    def run(caps):
+        arr = (S.GroupParams * nb)()
+        for b in range(nb):
+            arr[b] = S.GroupParams(S.POLICY_PAPER, 32, 0.5, 0, int(caps[b]))
+        dev = torch.as_tensor(np.frombuffer(bytes(arr), dtype=np.uint8).copy(), device="cuda")
+        pl = Pipeline(batch, StepConfig(t_cand=1024, hydro_t_cand=1024), gp_box=dev)
+        pl.ctx.status_clear()
+        pl.step()
+        _sync()
+        st = pl.ctx.status()
+        assert st["flags"] == 0
+        return st, pl.sorted_numpy(), pl.outputs_numpy()
+
+    st0, s0, o0 = run(np.zeros(nb, np.int64))
+    st1, s1, o1 = run(np.where(np.arange(nb) % 2 == 0, 64, 0))
+    assert st1["n_overflow"] > st0["n_overflow"]
+    assert np.array_equal(s0["h"], s1["h"]) and np.array_equal(s0["rho"], s1["rho"])
+    for k in o0:
+        assert np.array_equal(o0[k], o1[k]), k

@@ -113,3 +113,33 @@ def test_unconverged_counts_match_the_oracle(plum):
     assert st["n_not_converged"] == int((r.converged == 0).sum()) > 0
     assert np.array_equal(sn["h"][act], r.h)
     assert np.array_equal(o["nngb"][act], r.nngb)
+
+
+def test_schedule_statistics_follow_the_trace_switch():
+    """With tracing on, the status reports every workgroup of the density
+    group kernel and every wave of the hydro member kernel that ran, a span
+    within the pass and a tail within the span; with tracing off, nothing,
+    and the results are the same bits either way."""
+    import torch
+    w = W.lognormal_hydro(n=32768, grid=32, seed=5)
+    cfg = StepConfig(n_leaf=32, n_group_max=24, f=0.5, t_cand=1024, hydro_t_cand=1024)
+    pl = Pipeline(w, cfg)
+    pl.step()
+    _sync()
+    st = pl.ctx.status()
+    assert st["sched_units"] == [0, 0] and st["sched_span_us"] == [0.0, 0.0]
+    ref = pl.outputs_numpy()
+    pl.ctx.set_trace(True)
+    pl.step()
+    _sync()
+    st = pl.ctx.status()
+    pl.ctx.set_trace(False)
+    for k in range(2):
+        assert st["sched_units"][k] > 0
+        assert 0.0 < st["sched_span_us"][k] < 1e6
+        assert 0.0 <= st["sched_tail_us"][k] <= st["sched_span_us"][k]
+    out = pl.outputs_numpy()
+    for key in ("nngb", "iters", "ax", "ay", "az", "dudt", "vsigmax"):
+        assert np.array_equal(out[key], ref[key]), key
+    with pytest.raises(S.SfcError):
+        pl.ctx._check(pl.ctx.L.sfc_ctx_set_trace(pl.ctx.h, 2))
