@@ -1311,7 +1311,9 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
 };
 
 // ------------------------------------------------------------------ group workgroups
-// One workgroup of GW waves per group, groups taken from per-XCD work
+// One workgroup of W waves per group (four; two for small neighbour counts,
+// with at most GC_SMALL candidates staged, so that eight groups share a CU),
+// groups taken from per-XCD work
 // queues.  The group's superset is staged once into LDS: the FP64 positions
 // of its first C candidates, with the mass (density) or h_j and the particle
 // index (hydro); a superset larger than C reads the rest from global memory.
@@ -1324,10 +1326,11 @@ template <int MODE, class F, class Q = Fifo> struct StreamVisit {
 // the test decides on those differences outside a band E = 2^-44 (L h + h^2)
 // around h^2 (the two evaluations differ by less than 2^-48 L h + 2^-50 h^2),
 // and on the canonical r^2 of the raw coordinates inside it.
-constexpr int GW = 4;               // waves per group workgroup
+constexpr int GW = 4;               // waves per group workgroup (2 for small neighbour counts)
 constexpr int GKB = 4;              // candidate chunks a wave holds during a round
 constexpr int GSTG = 4;             // candidates a thread stages per pass
 constexpr int GC_MAX = 1024;        // staged candidates at most
+constexpr int GC_SMALL = 512;       // staged candidates at most for two waves per group
 constexpr int GMR = 32;             // members whose masks over the staged chunks are kept
 constexpr int GFB = 1;              // batches a group wave's FIFO hands over at once
 
@@ -1365,13 +1368,13 @@ struct GLds {
     float *cm;            // [C] staged candidates: m_j
     int32_t *mcnt;        // [3][64] neighbour counts of member m in round r (row r % 3)
     int32_t *ctl;         // [8]: the group taken
-    char *fifo;           // GW FIFOs of 128 * (batches at once) entries
+    char *fifo;           // one FIFO of 128 * (batches at once) entries per wave
     int C;
 };
-__host__ __device__ constexpr size_t glds_bytes(int C)
+__host__ __device__ constexpr size_t glds_bytes(int C, int W)
 {
     return (size_t)C * 28 + (size_t)8 * GMR * (C / 64) + 8 * 64 * 2 + 3 * 64 * 4 + 8 * 4 +
-           (size_t)GW * 128 * GFB * 4;
+           (size_t)W * 128 * GFB * 4;
 }
 __device__ __forceinline__ GLds glds_carve(char *p, int C)
 {
@@ -1408,16 +1411,16 @@ struct GCand {
 // their positions and masses.  The slots past nc up to the end of its chunk
 // get NaN positions, on which every test fails.  Each pass loads GSTG
 // indices per thread, then their records.
-__device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc)
+template <int W> __device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc)
 {
     const int n = min(gc.nc, S.C);
     const int npad = min((gc.nc + 63) & ~63, S.C);
     const double nan = __builtin_nan("");
-    for (int base = 0; base < npad; base += GSTG * GW * 64) {
+    for (int base = 0; base < npad; base += GSTG * W * 64) {
         int j[GSTG];
 #pragma unroll
         for (int u = 0; u < GSTG; u++) {
-            const int t = base + u * GW * 64 + (int)threadIdx.x;
+            const int t = base + u * W * 64 + (int)threadIdx.x;
             j[u] = t < n ? gc.cg[t] : -1;
         }
         double4 p[GSTG];
@@ -1425,7 +1428,7 @@ __device__ __forceinline__ void stage_cands(const GLds &S, const GCand &gc)
         for (int u = 0; u < GSTG; u++) p[u] = gc.p64[j[u] < 0 ? 0 : j[u]];
 #pragma unroll
         for (int u = 0; u < GSTG; u++) {
-            const int t = base + u * GW * 64 + (int)threadIdx.x;
+            const int t = base + u * W * 64 + (int)threadIdx.x;
             if (t < npad) {
                 const bool v = j[u] >= 0;
                 S.cx[t] = v ? p[u].x : nan;
@@ -1554,11 +1557,11 @@ __device__ __forceinline__ GMem grp_members(const Geom &geo, const GroupArg &ga,
 }
 
 // One filter round (all waves of the workgroup) of the members in `ev`: wave
-// w takes blocks w, w + GW, ... of GKB chunks, holds their candidates in
+// w takes blocks w, w + W, ... of GKB chunks, holds their candidates in
 // registers and tests them against every member of ev (r < h_m; member data
 // from lane m by readlane).  Member m's mask over staged chunk c goes to
 // S.rows[m * (C / 64) + c] (m < GMR); the counts are added to cnt_m[m].
-template <bool WRAP>
+template <bool WRAP, int W>
 __device__ __forceinline__ void grp_round(const GLds &S, const GCand &gc, const GSup &s, double L,
                                           uint64_t ev, const GMem &gm, int32_t *cnt_m)
 {
@@ -1572,7 +1575,7 @@ __device__ __forceinline__ void grp_round(const GLds &S, const GCand &gc, const 
     const double limv = gm.h * gm.h;
     const double Ev = WRAP ? 0x1p-44 * (L * gm.h + gm.h * gm.h) : 0.0;
     int cntv = 0;
-    for (int cb = wv * GKB; cb < nch; cb += GW * GKB) {
+    for (int cb = wv * GKB; cb < nch; cb += W * GKB) {
         double x[GKB], y[GKB], z[GKB];
 #pragma unroll
         for (int u = 0; u < GKB; u++) {
@@ -1953,8 +1956,8 @@ __device__ __forceinline__ int dens_emit(const DensK &k, const GLds &S, const GC
 // k_dens_solo with the state they reached; every member that finished is
 // then streamed by one wave into its sums from its masks of the last round,
 // and wave 0 finishes rho, drho/dh and f of all of them, one lane each.
-template <int KER, typename ACC>
-__global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_dgrp(DensK k)
+template <int KER, typename ACC, int W>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_dgrp(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const unsigned long long t_start = wall_clock64();
@@ -1987,15 +1990,15 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
             S.mcnt[lane] = 0;
             S.mcnt[64 + lane] = 0;
         }
-        if (!(s.flags & GSUP_SOLO)) stage_cands(S, gc);
+        if (!(s.flags & GSUP_SOLO)) stage_cands<W>(S, gc);
         __syncthreads();
         for (int round = 0; ev && round <= k.max_iter; round++) {
             int32_t *cnt = S.mcnt + 64 * (round % 3);
             if (wv == 0) S.mcnt[64 * ((round + 1) % 3) + lane] = 0;
             if (wrap)
-                grp_round<true>(S, gc, s, bx.L, ev, gm, cnt);
+                grp_round<true, W>(S, gc, s, bx.L, ev, gm, cnt);
             else
-                grp_round<false>(S, gc, s, bx.L, ev, gm, cnt);
+                grp_round<false, W>(S, gc, s, bx.L, ev, gm, cnt);
             __syncthreads();
             if (wv == 0) ws.tests += (unsigned long long)popc64(ev) * (unsigned long long)s.nc;
             if ((ev >> lane) & 1ull) {
@@ -2032,13 +2035,13 @@ __global__ __launch_bounds__(GW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
             ws.iters += (uint32_t)uni(wave_sum_i(done ? it : 0));
             ws.not_conv += (uint32_t)popc64(ballot(done && !conv));
         }
-        // the r-th member that finished is streamed by wave r mod GW (the
+        // the r-th member that finished is streamed by wave r mod W (the
         // masks and the staged superset are complete since the last barrier)
         uint64_t rest = dn;
         for (int r = 0; rest; r++) {
             const int m = ctz64(rest);
             rest &= rest - 1ull;
-            if (r % GW != wv) continue;
+            if (r % W != wv) continue;
             const int c = wrap ? dens_emit<KER, ACC, true>(k, S, gc, s, bx.L, wrap, gm, m, fifo)
                                : dens_emit<KER, ACC, false>(k, S, gc, s, bx.L, wrap, gm, m, fifo);
             ws.pairs += (unsigned long long)c;
@@ -2825,7 +2828,6 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     const sfc_density_params &dp = a.dp;
     const int T = dp.t_cand;
     auto ks = k_dens_solo<KER, ACC>;
-    auto kg = k_dgrp<KER, ACC>;
     const size_t lds_s = MEM_WAVES * mem_lds_bytes(T, true);
     hipError_t e = allow_lds(ks, lds_s);
     if (e != hipSuccess) return e;
@@ -2873,14 +2875,23 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
     k.trace = a.trace ? 1 : 0;
-    k.C = T < GC_MAX ? T : GC_MAX;
+    // small neighbour counts give small supersets (about (1 + f)^3 N_ngb, a
+    // few N_ngb): then two waves per group and at most 512 staged candidates
+    // (19 KB of LDS), so that eight groups share a CU; the rest of a larger
+    // superset is read from global memory
+    const bool small = 4 * dp.n_ngb <= GC_SMALL;
+    k.C = min(T, small ? GC_SMALL : GC_MAX);
     k.drift = dp.reuse ? sb.drift : nullptr;
     k.active = dp.reuse ? p.active : nullptr;
     k.dfr = sb.dfr;
     k.dstate = sb.dstate;
-    if ((e = launch_persistent(kg, s, k, 64 * GW, glds_bytes(k.C), sb.cu_count, p.n * GW)) !=
-        hipSuccess)
-        return e;
+    if (small)
+        e = launch_persistent(k_dgrp<KER, ACC, 2>, s, k, 64 * 2, glds_bytes(k.C, 2), sb.cu_count,
+                              p.n * 2);
+    else
+        e = launch_persistent(k_dgrp<KER, ACC, GW>, s, k, 64 * GW, glds_bytes(k.C, GW), sb.cu_count,
+                              p.n * GW);
+    if (e != hipSuccess) return e;
     ks<<<grid_s, 64 * MEM_WAVES, lds_s, s>>>(k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!dp.reuse) return hipSuccess;

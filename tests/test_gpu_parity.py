@@ -321,11 +321,14 @@ def test_density_h_loop_clustered(plum, plum_ref):
 @pytest.mark.parametrize("policy,cap,f,T", [(0, 1, 0.0, 1024), (0, 8, 0.0, 1024),
                                             (1, 16, 0.5, 1024), (1, 64, 0.5, 2048),
                                             (1, 64, 1.0, 4096), (1, 32, 0.5, 64),
+                                            (1, 16, 0.5, 512), (1, 32, 0.7, 256),
                                             (2, 64, 0.0, 2048)])
 def test_density_independent_of_grouping(policy, cap, f, T, plum, plum_ref):
     """Refinement gives each particle its true neighbours whatever its group,
     and the summation order depends only on the neighbour list: FP32 results
-    are bit-identical across groupings (and the overflow path, T=64)."""
+    are bit-identical across groupings (and the overflow path, T=64).  With
+    N_ngb = 64 the group kernel runs two waves per group and stages at most
+    512 candidates: the tiles above 512 read the rest from global memory."""
     say(f"[density] grouping policy={policy} cap={cap} f={f} T={T}")
     ob, s, act, r = plum_ref
     base = Pipeline(plum, StepConfig(policy=0, n_group_max=1, t_cand=1024))
