@@ -1332,7 +1332,7 @@ constexpr int GSTG = 4;             // candidates a thread stages per pass
 constexpr int GC_MAX = 1024;        // staged candidates at most
 constexpr int GC_SMALL = 512;       // staged candidates at most for two waves per group
 constexpr int GMR = 32;             // members whose masks over the staged chunks are kept
-constexpr int GFB = 1;              // batches a group wave's FIFO hands over at once
+constexpr int GFB = 2;              // batches a group wave's FIFO hands over at once
 
 // shift of a coordinate into the frame of the centre c: x - L when it lies
 // more than L/2 above c, x + L when more than L/2 below
