@@ -210,6 +210,8 @@ size_t layout(sfc_ctx *c, const sfc_dims &d, char *base)
     xb.drift = nullptr;
     xb.sel = nullptr;
     xb.dfr = b.take<int32_t>(n);
+    xb.gmark = b.take<int32_t>(n);
+    xb.glist = b.take<int32_t>(n);
     xb.cu_count = c ? c->cu : 0;
     SearchBufs xh = xb;
     if (d.keep_supersets) {

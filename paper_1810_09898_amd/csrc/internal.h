@@ -137,6 +137,7 @@ struct DevStatus {
     unsigned long long sum_tests;
     unsigned long long sum_pairs;
     unsigned long long n_dfr; // per pass: hydro members deferred to their own walks
+    unsigned long long n_glist; // reuse density pass: groups holding a member active now
     // with tracing on, per pass, for the density group kernel [0] and the
     // hydro member kernel [1], per XCD (each on a 128-byte line of its own):
     // the earliest start and the latest end of a workgroup (density) or wave
@@ -292,6 +293,8 @@ struct SearchBufs {
                                // then per-block partials
     int32_t *sel;     // [n] reuse: positions in the active list of the members active now
     int32_t *dfr;     // [n] hydro: positions in the active list of the members that walk alone
+    int32_t *gmark;   // [n] reuse: 1 for a kept group holding a member active now
+    int32_t *glist;   // [n] reuse: those groups (st->n_glist of them)
     int32_t cu_count;
 };
 struct DensityArgs {

@@ -827,6 +827,7 @@ __global__ void k_reset_pass(DevStatus *st, int pass)
         st->qctr2[32 * t] = 0;
     }
     if (t == 8) st->n_dfr = 0ull;
+    if (t == 9) st->n_glist = 0ull;
 }
 
 // Reuse: the positions in the active list of the members whose active flag
@@ -861,6 +862,48 @@ __global__ __launch_bounds__(256) void k_sel_members(const int32_t *__restrict__
 #pragma unroll
         for (int u = 0; u < SEL_CH; u++) {
             if ((m[u] >> lane) & 1ull) sel[b + mbcnt(m[u])] = c0 + 64 * u + lane;
+            b += popc64(m[u]);
+        }
+    }
+}
+
+// Reuse: the kept groups that hold a member active now.  First each
+// selected member marks its group (gmark cleared before), then the marked
+// groups are listed like the members (one atomic per SEL_CH blocks of 64).
+__global__ __launch_bounds__(256) void k_gmark(const int32_t *__restrict__ sel,
+                                               const unsigned long long *__restrict__ cnt,
+                                               const int32_t *__restrict__ grp,
+                                               int32_t *__restrict__ gmark)
+{
+    const int n = (int)*cnt;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) gmark[grp[sel[i]]] = 1;
+}
+__global__ __launch_bounds__(256) void k_glist(const int32_t *__restrict__ n_groups,
+                                               const int32_t *__restrict__ gmark,
+                                               int32_t *__restrict__ glist,
+                                               unsigned long long *__restrict__ cnt)
+{
+    const int G = *n_groups;
+    const int lane = lane_id();
+    const int nw = (int)(gridDim.x * blockDim.x) >> 6;
+    const int wv = (int)(blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    for (int c0 = wv * 64 * SEL_CH; c0 < G; c0 += nw * 64 * SEL_CH) {
+        uint64_t m[SEL_CH];
+        int total = 0;
+#pragma unroll
+        for (int u = 0; u < SEL_CH; u++) {
+            const int g = c0 + 64 * u + lane;
+            m[u] = ballot(g < G && gmark[g] != 0);
+            total += popc64(m[u]);
+        }
+        if (total == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(cnt, (unsigned long long)total);
+        int b = readlane_i((int)base, 0);
+#pragma unroll
+        for (int u = 0; u < SEL_CH; u++) {
+            if ((m[u] >> lane) & 1ull) glist[b + mbcnt(m[u])] = c0 + 64 * u + lane;
             b += popc64(m[u]);
         }
     }
@@ -1658,6 +1701,7 @@ struct DensK {
     const uint8_t *active;           // reused supersets: the members computed now
     int32_t *dfr;                    // members that finish on their own (st->n_dfr of them)
     double4 *dstate;                 // per active: h, bracket lo, hi and evaluations so far
+    const int32_t *glist;            // reuse: the groups holding a member active now, or NULL
     int n_ngb, dn, max_iter, fixed_h;
     int C;                           // candidates a group workgroup stages in LDS
     int trace; // schedule statistics (DevStatus::sched)
@@ -1965,13 +2009,15 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int lane = lane_id();
     const int wv = uni((int)(threadIdx.x >> 6));
     DEnt *fifo = (DEnt *)(S.fifo + (size_t)wv * 128 * GFB * sizeof(DEnt));
-    Queue wq = queue_open(k.st->qctr2, uni(*k.ga.n_groups));
+    // a reuse pass takes only the groups that hold a member active now
+    Queue wq = queue_open(k.st->qctr2, k.glist ? uni((int)k.st->n_glist) : uni(*k.ga.n_groups));
     WaveStats ws;
     // a reused superset: every particle may have moved by dl since the walk
     const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
     for (;;) {
-        const int g = wg_take(wq, S);
-        if (g < 0) break;
+        const int item = wg_take(wq, S);
+        if (item < 0) break;
+        const int g = k.glist ? uni(k.glist[item]) : item;
         const GSup s = load_gsup(k.ca.sup + g);
         const int a0 = uni(k.ga.goff[g]);
         const int M = min(uni(k.ga.goff[g + 1]) - a0, 64);
@@ -2106,6 +2152,7 @@ struct HydroK {
     const double4 *p64; // per particle: FP64 x, y, z, h (pair terms)
     const unsigned long long *drift; // reused supersets: largest displacement, h growth, or NULL
     const uint8_t *active;           // reused supersets: the members computed now
+    const int32_t *sel;              // reused supersets: the members active now, or NULL
     int32_t *dfr;                    // members that walk alone (st->n_dfr of them)
     sfc_hydro_out out;
     DevStatus *st;
@@ -2461,13 +2508,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
     const unsigned long long t_start = wall_clock64();
     HEnt *fifo = (HEnt *)(lds_raw + (size_t)uni((int)(threadIdx.x >> 6)) * FIFO_BYTES);
     const int lane = lane_id();
-    const int A = uni(*k.ga.n_act);
+    // a reuse pass takes only the members active now (listed in sel)
+    const int A = k.sel ? uni((int)k.drift[3]) : uni(*k.ga.n_act);
     const ItemRange ar = item_range(A);
     WaveStats ws;
     // reused supersets: the largest displacement and h growth since the walk
     const double dl = k.drift ? __longlong_as_double((long long)k.drift[0]) : 0.0;
     const double dh = k.drift ? __longlong_as_double((long long)k.drift[1]) : 0.0;
-    for (int a = ar.i; a < ar.end; a += ar.stride) {
+    for (int item = ar.i; item < ar.end; item += ar.stride) {
+        const int a = k.sel ? uni(k.sel[item]) : item;
         const Member M = member(k.g, k.ga, k.ca, a);
         if (k.active && !uni(k.active[M.i])) continue; // reuse: the members active now
         const bool kept = !k.drift || (M.h + M.d + dl <= M.s.cov && M.d + dl + dh <= M.s.rs);
@@ -2853,6 +2902,18 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
         // the kept supersets: the walk is skipped, the drift bounds them
         k_reset_pass<<<1, 64, 0, s>>>(st, 0);
         e = launch_drift(s, p, nullptr, g, sb);
+        // the groups holding a member active now
+        if (e == hipSuccess) e = launch_fill_i32(s, sb.gmark, 0, p.n);
+        if (e == hipSuccess) {
+            k_gmark<<<1024, 256, 0, s>>>(sb.sel, sb.drift + 3, gs.grp, sb.gmark);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            const int64_t wg = (p.n + 256 * SEL_CH - 1) / (256 * SEL_CH);
+            k_glist<<<(unsigned)(wg < 4096 ? wg : 4096), 256, 0, s>>>(g.n_groups, sb.gmark, sb.glist,
+                                                                     &st->n_glist);
+            e = hipGetLastError();
+        }
     } else {
         e = launch_walk(s, p, t, g, gs, st, T, dp.skin, 0);
     }
@@ -2883,6 +2944,7 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.C = min(T, small ? GC_SMALL : GC_MAX);
     k.drift = dp.reuse ? sb.drift : nullptr;
     k.active = dp.reuse ? p.active : nullptr;
+    k.glist = dp.reuse ? sb.glist : nullptr;
     k.dfr = sb.dfr;
     k.dstate = sb.dstate;
     if (small)
@@ -2972,6 +3034,7 @@ hipError_t launch_hydro(hipStream_t s, const PartDev &p, const TreeDev &t, const
     k.ell = hp.ell;
     k.drift = hp.reuse ? sb.drift : nullptr;
     k.active = hp.reuse ? p.active : nullptr;
+    k.sel = hp.reuse ? sb.sel : nullptr;
     k.dfr = sb.dfr;
     const int64_t n = p.n;
     const bool f32 = hp.accum == SFC_ACCUM_F32;

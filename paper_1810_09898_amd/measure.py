@@ -336,10 +336,7 @@ def main():
         reuse_scan(w, cfg, args.steps, [float(v) for v in args.reuse.split(",")],
                    [float(v) for v in args.fracs.split(",")])
     elif args.workload == "plummer_batch":
-        # walk skin 1.1: the batch's groups are small (about two members),
-        # so a member whose h grows would otherwise leave its superset
-        cfg = StepConfig(n_leaf=16, n_group_max=32, f=0.5, t_cand=1024, hydro_t_cand=1024,
-                         skin=1.1)
+        cfg = StepConfig(n_leaf=16, n_group_max=32, f=0.5, t_cand=1024, hydro_t_cand=1024)
         run(w, cfg, "plummer_batch (hand rule per box)", args.steps,
             gp_box=autotune.per_box_params(w, autotune.batch_rule))
         if args.tune_boxes:
