@@ -260,11 +260,13 @@ struct Queue {
     int32_t *ctr; // [8 * 32]: counter x at ctr[32 * x]
     int n, per, xcd, xs;
     int cur, end; // items left of the current take
+    int qb;       // items per take
 };
-__device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items)
+__device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items, int qb = QB)
 {
     Queue q;
     q.ctr = ctr;
+    q.qb = qb;
     q.n = n_items;
     q.per = (n_items + 7) >> 3;
     q.xcd = blockIdx.x & 7;
@@ -279,12 +281,12 @@ __device__ __forceinline__ int queue_next(Queue &q)
     while (q.xs < 8) {
         const int x = (q.xcd + q.xs) & 7;
         int t = 0;
-        if (lane_id() == 0) t = atomicAdd(&q.ctr[32 * x], QB);
+        if (lane_id() == 0) t = atomicAdd(&q.ctr[32 * x], q.qb);
         t = uni(t);
         const int item = x * q.per + t;
         if (t < q.per && item < q.n) {
             q.cur = item + 1;
-            q.end = min(min(x * q.per + q.per, q.n), item + QB);
+            q.end = min(min(x * q.per + q.per, q.n), item + q.qb);
             return item;
         }
         q.xs++;
@@ -2496,6 +2498,8 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
 }
 
 
+constexpr int HQB = 4; // members per take in the hydro member kernel's dynamic part
+
 // Hydro, one wave per active particle: the group superset filtered to
 // r < max(h_i, h_j), j != i, decided on the FP32 positions and h wherever
 // that is safely away from the edge and by the FP64 test inside the band,
@@ -2510,20 +2514,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
     const int lane = lane_id();
     // a reuse pass takes only the members active now (listed in sel)
     const int A = k.sel ? uni((int)k.drift[3]) : uni(*k.ga.n_act);
-    const ItemRange ar = item_range(A);
+    // the first seven eighths in a static split (the waves of a workgroup
+    // on consecutive members, which share a superset in the CU's L1), the
+    // rest from the per-XCD queues, HQB members per take, so that the waves
+    // that finish their share early absorb the spread of the others
+    const int As = A - (A >> 3);
+    const ItemRange ar = item_range(As);
     WaveStats ws;
     // reused supersets: the largest displacement and h growth since the walk
     const double dl = k.drift ? __longlong_as_double((long long)k.drift[0]) : 0.0;
     const double dh = k.drift ? __longlong_as_double((long long)k.drift[1]) : 0.0;
-    for (int item = ar.i; item < ar.end; item += ar.stride) {
+    auto one = [&](int item) {
         const int a = k.sel ? uni(k.sel[item]) : item;
         const Member M = member(k.g, k.ga, k.ca, a);
-        if (k.active && !uni(k.active[M.i])) continue; // reuse: the members active now
+        if (k.active && !uni(k.active[M.i])) return; // reuse: the members active now
         const bool kept = !k.drift || (M.h + M.d + dl <= M.s.cov && M.d + dl + dh <= M.s.rs);
         if ((M.s.flags & GSUP_SOLO) || !kept) {
             ws.deferred++;
             if (lane == 0) k.dfr[atomicAdd(&k.st->n_dfr, 1ull)] = a;
-            continue;
+            return;
         }
         const bool wrap = (M.s.flags & GSUP_WRAP) || k.drift;
         HydroPair<KER, ACC, PHYS> hp = hydro_pair<KER, ACC, PHYS>(k, M.i, M.xi, M.yi, M.zi, M.bx.L, M.h,
@@ -2578,7 +2587,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC)
         }
         q.flush(hp);
         hydro_write<KER, ACC>(k, M.i, hp);
-    }
+    };
+    for (int item = ar.i; item < ar.end; item += ar.stride) one(item);
+    Queue tq = queue_open(k.st->qctr2, A - As, HQB);
+    for (int t = queue_next(tq); t >= 0; t = queue_next(tq)) one(As + t);
     ws.flush(k.st);
     if (k.trace && lane == 0) sched_mark(k.st, 1, t_start);
 }
