@@ -2498,7 +2498,7 @@ __global__ void k_hydro_prep(int64_t n, const float *__restrict__ m, const float
 }
 
 
-constexpr int HQB = 4; // members per take in the hydro member kernel's dynamic part
+constexpr int HQB = 8; // members per take in the hydro member kernel's dynamic part
 
 // Hydro, one wave per active particle: the group superset filtered to
 // r < max(h_i, h_j), j != i, decided on the FP32 positions and h wherever
