@@ -301,7 +301,7 @@ def main():
     roof = {"bound": "alu", "achieved": round(ach_ops, 3), "peak": round(peak_t, 2),
             "unit": "T lane-instructions/s", "frac": round(ach_ops / peak_t, 4),
             "traffic": traffic, "kernel": kname,
-            "kernels": ("k_dens_prep + k_walk + k_dgrp + k_dens_solo"
+            "kernels": ("k_dens_prep + k_walk + k_gcount + k_gorder + k_dgrp + k_dens_solo"
                         if kname == "density"
                         else "refit + k_hydro_prep + k_walk + k_hmem + k_hydro_solo"),
             "algorithmic_ops": int(kops),

@@ -123,6 +123,11 @@ __device__ __forceinline__ double fold(double d, double L)
 }
 
 // ------------------------------------------------------- status block
+// cost classes of the density group kernel's order of the groups, and the
+// groups per workgroup of the kernels that make it
+constexpr int GO_K = 16;
+constexpr int GO_CH = 512;
+
 struct DevStatus {
     uint32_t flags;
     int32_t n_nodes;
@@ -151,6 +156,13 @@ struct DevStatus {
     unsigned long long cand_top[8 * 16]; // cand_top[16 * x]
     int32_t qctr[8 * 32];                // qctr[32 * x]: the walk kernel's
     int32_t qctr2[8 * 32];               // qctr2[32 * x]: the group kernels'
+    // per density pass, the order of the groups for the group kernel: the
+    // total cost, and per eighth and cost class the groups and the slots
+    // handed out so far
+    unsigned long long go_wtot;
+    int32_t go_on; // the order was written (else the index order holds)
+    int32_t go_tot[8 * GO_K];
+    int32_t go_cur[8 * GO_K];
 };
 
 // per-group record written by the walk kernel
@@ -294,7 +306,8 @@ struct SearchBufs {
     int32_t *sel;     // [n] reuse: positions in the active list of the members active now
     int32_t *dfr;     // [n] hydro: positions in the active list of the members that walk alone
     int32_t *gmark;   // [n] reuse: 1 for a kept group holding a member active now
-    int32_t *glist;   // [n] reuse: those groups (st->n_glist of them)
+    int32_t *glist;   // [n] reuse: those groups (st->n_glist of them); otherwise every group,
+                      // in the density group kernel's order (when st->go_on is set)
     int32_t cu_count;
 };
 struct DensityArgs {

@@ -274,6 +274,16 @@ __device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items, int qb = 
     q.cur = q.end = 0;
     return q;
 }
+// Items per take for the walk and the density group kernel: with many
+// items per taker (at least GQ_MANY each) a take hands out GQB of them, so
+// the atomics are fewer and the few items that one take holds back at the
+// end are a small part of a taker's work; otherwise one.
+constexpr int GQB = 4;
+constexpr int GQ_MANY = 256;
+__device__ __forceinline__ int queue_qb(int n_items, int takers, int qb)
+{
+    return (int64_t)n_items >= (int64_t)GQ_MANY * takers ? qb : 1;
+}
 // next item, or -1 when every range is used up
 __device__ __forceinline__ int queue_next(Queue &q)
 {
@@ -830,6 +840,11 @@ __global__ void k_reset_pass(DevStatus *st, int pass)
     }
     if (t == 8) st->n_dfr = 0ull;
     if (t == 9) st->n_glist = 0ull;
+    if (t == 10) st->go_wtot = 0ull;
+    for (int j = t; j < 8 * GO_K; j += blockDim.x) {
+        st->go_tot[j] = 0;
+        st->go_cur[j] = 0;
+    }
 }
 
 // Reuse: the positions in the active list of the members whose active flag
@@ -911,6 +926,141 @@ __global__ __launch_bounds__(256) void k_glist(const int32_t *__restrict__ n_gro
     }
 }
 
+// Order of the groups for the density group kernel.  Its queues hand each
+// XCD the groups of one eighth of the index range, in index order
+// (neighbouring groups share candidates in that XCD's L2).  A large group
+// taken near the end of an eighth then runs alone while the other
+// workgroups have finished.  So the heavy groups of each eighth move to its
+// front, costliest first; every other group keeps its index order after
+// them.  A group's cost is its member count times its
+// superset size, w; class c holds the groups with w in
+// [2^(c+GO_LOG0), 2^(c+GO_LOG0+1)) (the lowest and the highest class
+// open-ended; a group without a kept superset in class 0), and a class is
+// heavy when its upper bound reaches 1/GO_BETA of a workgroup's fair share
+// of the total cost (sum of w over the number of workgroups).  Two passes
+// over chunks of GO_CH groups: class totals per eighth and the total cost
+// (atomics into the status block, cleared by the pass reset), then each
+// chunk takes its slots per class with one atomic and scatters its groups
+// in index order; the chunks of one class follow each other in the order
+// of their atomics.  With many groups per workgroup (GQ_MANY or more) the
+// groups are small against a workgroup's share and the order stays the
+// index order (go_on = 0): no pass writes it and the group kernel reads no
+// list.
+constexpr int GO_LOG0 = 9;
+constexpr int GO_BETA = 32;
+struct GoSpan {
+    int x, g0, g1; // eighth, chunk [g0, g1)
+};
+__device__ __forceinline__ GoSpan go_span(int G)
+{
+    const int per = (G + 7) >> 3;
+    const int nch = (per + GO_CH - 1) / GO_CH;
+    GoSpan sp;
+    sp.x = nch > 0 ? (int)blockIdx.x / nch : 8;
+    const int c = nch > 0 ? (int)blockIdx.x % nch : 0;
+    const int e0 = sp.x * per, e1 = min((sp.x + 1) * per, G);
+    sp.g0 = e0 + c * GO_CH;
+    sp.g1 = sp.x < 8 ? min(sp.g0 + GO_CH, e1) : sp.g0;
+    return sp;
+}
+// cost class of group g
+__device__ __forceinline__ int go_raw(const GroupArg &ga, const GSup *sup, int g, int64_t &w)
+{
+    const GSup &sp = sup[g];
+    w = (sp.flags & GSUP_SOLO) ? 0 : (int64_t)(ga.goff[g + 1] - ga.goff[g]) * sp.nc;
+    const int lg = w > 0 ? 63 - __clzll(w) : 0;
+    return min(max(lg - GO_LOG0, 0), GO_K - 1);
+}
+// grid: 8 x (groups per eighth / GO_CH) workgroups at least
+__device__ __forceinline__ bool go_wanted(int G, int units)
+{
+    return (int64_t)G < (int64_t)GQ_MANY * units;
+}
+__global__ __launch_bounds__(256) void k_gcount(GroupArg ga, const GSup *__restrict__ sup, int units,
+                                               DevStatus *st)
+{
+    __shared__ int h[GO_K];
+    __shared__ unsigned long long ws;
+    const int G = *ga.n_groups;
+    if (!go_wanted(G, units)) return;
+    const GoSpan sp = go_span(G);
+    if (sp.g0 >= sp.g1) return;
+    if (threadIdx.x < GO_K) h[threadIdx.x] = 0;
+    if (threadIdx.x == 0) ws = 0ull;
+    __syncthreads();
+    unsigned long long mine = 0ull;
+    for (int g = sp.g0 + (int)threadIdx.x; g < sp.g1; g += 256) {
+        int64_t w;
+        atomicAdd(&h[go_raw(ga, sup, g, w)], 1);
+        mine += (unsigned long long)w;
+    }
+    if (mine) atomicAdd(&ws, mine);
+    __syncthreads();
+    if (threadIdx.x < GO_K && h[threadIdx.x]) atomicAdd(&st->go_tot[sp.x * GO_K + threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x == 0 && ws) atomicAdd(&st->go_wtot, ws);
+}
+// the same grid: the positions of the chunk's groups in the order, for
+// `units` workgroups of the group kernel; block 0 also sets go_on
+__global__ __launch_bounds__(256) void k_gorder(GroupArg ga, const GSup *__restrict__ sup, int units,
+                                               int32_t *__restrict__ order, DevStatus *st)
+{
+    __shared__ int base[GO_K], hk[GO_K], wc[4][GO_K];
+    __shared__ int kmin_s;
+    const int G = *ga.n_groups;
+    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    if (blockIdx.x == 0 && t == 0) st->go_on = go_wanted(G, units) ? 1 : 0;
+    if (!go_wanted(G, units)) return;
+    const GoSpan sp = go_span(G);
+    if (sp.g0 >= sp.g1) return;
+    const int per = (G + 7) >> 3;
+    if (t == 0) {
+        const double share = (double)st->go_wtot / max(units, 1);
+        int km = 0; // heavy: 2^(k + GO_LOG0 + 1) >= share / GO_BETA
+        while (km < GO_K - 1 && ldexp(1.0, km + GO_LOG0 + 1) * GO_BETA < share) km++;
+        kmin_s = km;
+    }
+    if (t < GO_K) hk[t] = 0;
+    __syncthreads();
+    const int kmin = kmin_s;
+    // effective class: a heavy class, or kmin - 1 for every other group
+    int kk[(GO_CH + 255) / 256];
+#pragma unroll
+    for (int u = 0; u < (GO_CH + 255) / 256; u++) {
+        const int g = sp.g0 + 256 * u + t;
+        int64_t w;
+        kk[u] = g < sp.g1 ? max(go_raw(ga, sup, g, w), kmin - 1) : -2;
+        if (kk[u] >= 0) atomicAdd(&hk[kk[u]], 1);
+    }
+    __syncthreads();
+    if (t < GO_K) {
+        int above = 0; // groups of the eighth in higher effective classes
+        for (int k = max(t + 1, kmin); k < GO_K; k++) above += st->go_tot[sp.x * GO_K + k];
+        base[t] = hk[t] ? sp.x * per + above + atomicAdd(&st->go_cur[sp.x * GO_K + t], hk[t]) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (GO_CH + 255) / 256; u++) {
+        const int g = sp.g0 + 256 * u + t;
+        const int k = kk[u];
+        int r = 0;
+#pragma unroll
+        for (int q = 0; q < GO_K; q++) {
+            const uint64_t m = ballot(k == q);
+            if (k == q) r = mbcnt(m);
+            if (lane == 0) wc[wv][q] = popc64(m);
+        }
+        __syncthreads();
+        if (k >= 0) {
+            int o = base[k] + r;
+            for (int w = 0; w < wv; w++) o += wc[w][k];
+            order[o] = g;
+        }
+        __syncthreads();
+        if (t < GO_K) base[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        __syncthreads();
+    }
+}
+
 // After a reuse pass: every particle active now was a member of a kept group
 __global__ void k_reuse_check(const unsigned long long *drift, DevStatus *st)
 {
@@ -927,7 +1077,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     int *lst = (int *)lds_raw; // [2 * LCAP + 64]: item lists of the level walk, owner marks
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
-    Queue wq = queue_open(k.st->qctr, G);
+    Queue wq = queue_open(k.st->qctr, G, queue_qb(G, (int)gridDim.x, GQB));
     WaveStats ws;
     // candidates are placed in chunks taken by this wave: up to 8192 slots,
     // at most a quarter of a wave's fair share of the buffer, at least a tile
@@ -1396,6 +1546,7 @@ __device__ __forceinline__ int wave_sum_i(int v)
 
 // append the members in `dm` (lanes) to the list of members that finish on
 // their own, one atomic per group
+
 __device__ __forceinline__ void defer_members(uint64_t dm, int a, int32_t *dfr, DevStatus *st)
 {
     if (!dm) return;
@@ -1675,12 +1826,35 @@ __device__ __forceinline__ void sched_mark(DevStatus *st, int k, unsigned long l
     atomicAdd(&q[3], 1ull);
 }
 
-// the group taken by the workgroup (wave 0 takes it; -1: none left)
-__device__ __forceinline__ int wg_take(Queue &q, const GLds &S)
+// The groups of a workgroup: wave 0 takes them from the queue and looks
+// each up in the list `gl` (NULL: the item is the group), one group ahead,
+// so that the look-up of the next group runs while the workgroup works on
+// the current one.
+
+struct WgTake {
+    Queue q;
+    const int32_t *gl;
+    int next; // wave 0: the group after the current one (-1: none left)
+};
+__device__ __forceinline__ int wg_resolve(WgTake &w)
+{
+    const int item = queue_next(w.q);
+    return item < 0 ? -1 : (w.gl ? w.gl[item] : item);
+}
+__device__ __forceinline__ WgTake wg_open(int32_t *ctr, int n_items, const int32_t *gl)
+{
+    WgTake w;
+    w.q = queue_open(ctr, n_items, queue_qb(n_items, (int)gridDim.x, GQB));
+    w.gl = gl;
+    w.next = threadIdx.x < 64 ? wg_resolve(w) : -1;
+    return w;
+}
+// the group taken by the workgroup (-1: none left)
+__device__ __forceinline__ int wg_take(WgTake &w, const GLds &S)
 {
     if (threadIdx.x < 64) {
-        const int g = queue_next(q);
-        if (threadIdx.x == 0) S.ctl[0] = g;
+        if (threadIdx.x == 0) S.ctl[0] = w.next;
+        w.next = w.next < 0 ? -1 : wg_resolve(w);
     }
     __syncthreads();
     return uni(S.ctl[0]);
@@ -1703,7 +1877,10 @@ struct DensK {
     const uint8_t *active;           // reused supersets: the members computed now
     int32_t *dfr;                    // members that finish on their own (st->n_dfr of them)
     double4 *dstate;                 // per active: h, bracket lo, hi and evaluations so far
-    const int32_t *glist;            // reuse: the groups holding a member active now, or NULL
+    const int32_t *glist;            // reuse: the groups holding a member active now
+                                     // (st->n_glist of them), or NULL
+    const int32_t *gord;             // otherwise: every group, in the order to take them
+                                     // when st->go_on is set
     int n_ngb, dn, max_iter, fixed_h;
     int C;                           // candidates a group workgroup stages in LDS
     int trace; // schedule statistics (DevStatus::sched)
@@ -2012,14 +2189,14 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int wv = uni((int)(threadIdx.x >> 6));
     DEnt *fifo = (DEnt *)(S.fifo + (size_t)wv * 128 * GFB * sizeof(DEnt));
     // a reuse pass takes only the groups that hold a member active now
-    Queue wq = queue_open(k.st->qctr2, k.glist ? uni((int)k.st->n_glist) : uni(*k.ga.n_groups));
+    const int32_t *gl = k.glist ? k.glist : (k.gord && uni(k.st->go_on) ? k.gord : nullptr);
+    WgTake wq = wg_open(k.st->qctr2, k.glist ? uni((int)k.st->n_glist) : uni(*k.ga.n_groups), gl);
     WaveStats ws;
     // a reused superset: every particle may have moved by dl since the walk
     const double dl = k.drift ? __longlong_as_double((long long)*k.drift) : 0.0;
     for (;;) {
-        const int item = wg_take(wq, S);
-        if (item < 0) break;
-        const int g = k.glist ? uni(k.glist[item]) : item;
+        const int g = wg_take(wq, S);
+        if (g < 0) break;
         const GSup s = load_gsup(k.ca.sup + g);
         const int a0 = uni(k.ga.goff[g]);
         const int M = min(uni(k.ga.goff[g + 1]) - a0, 64);
@@ -2907,6 +3084,17 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     }
     SearchBufs gs = sb;
     if (priv <= sb.cand_cap / 2) gs.cand_cap = sb.cand_cap - priv;
+    // small neighbour counts give small supersets (about (1 + f)^3 N_ngb, a
+    // few N_ngb): then two waves per group and at most 512 staged candidates
+    // (19 KB of LDS), so that eight groups share a CU; the rest of a larger
+    // superset is read from global memory
+    const bool small = 4 * dp.n_ngb <= GC_SMALL;
+    const int C = min(T, small ? GC_SMALL : GC_MAX);
+    auto kg = small ? k_dgrp<KER, ACC, 2> : k_dgrp<KER, ACC, GW>;
+    const int wgt = 64 * (small ? 2 : GW);
+    const size_t lds_g = glds_bytes(C, small ? 2 : GW);
+    if ((e = allow_lds(kg, lds_g)) != hipSuccess) return e;
+    const unsigned units = grid_size(kg, wgt, lds_g, sb.cu_count, p.n * (wgt / 64));
     k_dens_prep<<<(unsigned)((p.n + 255) / 256), 256, 0, s>>>(p.n, p.x, p.y, p.z, p.h, p.m, sb.pos4,
                                                               sb.p64, a.keep ? sb.snap : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -2928,6 +3116,14 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
         }
     } else {
         e = launch_walk(s, p, t, g, gs, st, T, dp.skin, 0);
+        // every group; the heavy ones of an eighth first
+        const unsigned go_grid = (unsigned)(8 * (((p.n + 7) / 8 + GO_CH - 1) / GO_CH));
+        if (e == hipSuccess) {
+            const GroupArg ga = make_groups(g, T);
+            k_gcount<<<go_grid, 256, 0, s>>>(ga, gs.sup, (int)units, st);
+            k_gorder<<<go_grid, 256, 0, s>>>(ga, gs.sup, (int)units, sb.glist, st);
+            e = hipGetLastError();
+        }
     }
     if (e != hipSuccess) return e;
     DensK k;
@@ -2948,24 +3144,15 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.max_iter = dp.max_iter;
     k.fixed_h = dp.fixed_h;
     k.trace = a.trace ? 1 : 0;
-    // small neighbour counts give small supersets (about (1 + f)^3 N_ngb, a
-    // few N_ngb): then two waves per group and at most 512 staged candidates
-    // (19 KB of LDS), so that eight groups share a CU; the rest of a larger
-    // superset is read from global memory
-    const bool small = 4 * dp.n_ngb <= GC_SMALL;
-    k.C = min(T, small ? GC_SMALL : GC_MAX);
+    k.C = C;
     k.drift = dp.reuse ? sb.drift : nullptr;
     k.active = dp.reuse ? p.active : nullptr;
     k.glist = dp.reuse ? sb.glist : nullptr;
+    k.gord = dp.reuse ? nullptr : sb.glist;
     k.dfr = sb.dfr;
     k.dstate = sb.dstate;
-    if (small)
-        e = launch_persistent(k_dgrp<KER, ACC, 2>, s, k, 64 * 2, glds_bytes(k.C, 2), sb.cu_count,
-                              p.n * 2);
-    else
-        e = launch_persistent(k_dgrp<KER, ACC, GW>, s, k, 64 * GW, glds_bytes(k.C, GW), sb.cu_count,
-                              p.n * GW);
-    if (e != hipSuccess) return e;
+    kg<<<units, wgt, lds_g, s>>>(k);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     ks<<<grid_s, 64 * MEM_WAVES, lds_s, s>>>(k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!dp.reuse) return hipSuccess;

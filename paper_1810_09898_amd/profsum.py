@@ -72,7 +72,7 @@ def _dispatches(rows):
     return out
 
 
-DENS_CALL = ("k_dens_prep", "k_reset_pass", "k_walk", "k_dgrp")
+DENS_CALL = ("k_dens_prep", "k_reset_pass", "k_walk", "k_gcount", "k_gorder", "k_dgrp")
 HYDRO_CALL = ("k_tree_leaves", "k_tree_up3", "k_tree_nchild", "k_hydro_prep", "k_reset_pass",
               "k_walk", "k_hmem")
 
