@@ -274,10 +274,11 @@ __device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items, int qb = 
     q.cur = q.end = 0;
     return q;
 }
-// Items per take for the walk and the density group kernel: with many
-// items per taker (at least GQ_MANY each) a take hands out GQB of them, so
-// the atomics are fewer and the few items that one take holds back at the
-// end are a small part of a taker's work; otherwise one.
+// Items per take: the walk takes GQB groups per atomic; the density group
+// kernel too when it has many groups per workgroup (at least GQ_MANY each),
+// so the atomics are fewer and the few items that one take holds back at
+// the end are a small part of a taker's work; otherwise one (its groups
+// cost more and vary more, and a held-back one would lengthen the tail).
 constexpr int GQB = 4;
 constexpr int GQ_MANY = 256;
 __device__ __forceinline__ int queue_qb(int n_items, int takers, int qb)
@@ -1077,7 +1078,7 @@ __global__ __launch_bounds__(64) void k_walk(WalkK k)
     int *lst = (int *)lds_raw; // [2 * LCAP + 64]: item lists of the level walk, owner marks
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
-    Queue wq = queue_open(k.st->qctr, G, queue_qb(G, (int)gridDim.x, GQB));
+    Queue wq = queue_open(k.st->qctr, G, GQB);
     WaveStats ws;
     // candidates are placed in chunks taken by this wave: up to 8192 slots,
     // at most a quarter of a wave's fair share of the buffer, at least a tile
