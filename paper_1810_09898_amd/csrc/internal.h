@@ -156,6 +156,7 @@ struct DevStatus {
     unsigned long long cand_top[8 * 16]; // cand_top[16 * x]
     int32_t qctr[8 * 32];                // qctr[32 * x]: the walk kernel's
     int32_t qctr2[8 * 32];               // qctr2[32 * x]: the group kernels'
+    int32_t qctr3[8 * 32];               // qctr3[32 * x]: the density solo kernel's
     // per density pass, the order of the groups for the group kernel: the
     // total cost, and per eighth and cost class the groups and the slots
     // handed out so far

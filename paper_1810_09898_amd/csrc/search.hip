@@ -838,6 +838,7 @@ __global__ void k_reset_pass(DevStatus *st, int pass)
         st->cand_top[16 * t] = 0ull;
         st->qctr[32 * t] = 0;
         st->qctr2[32 * t] = 0;
+        st->qctr3[32 * t] = 0;
     }
     if (t == 8) st->n_dfr = 0ull;
     if (t == 9) st->n_glist = 0ull;
@@ -2289,9 +2290,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     extern __shared__ __align__(16) char lds_raw[];
     const MemLds S = mem_carve(lds_raw, k.ga.T, true);
     const int D = uni((int)k.st->n_dfr);
-    const ItemRange ar = item_range(D);
+    // the members cost from one superset pass to a walk per h evaluation:
+    // taken one at a time from the per-XCD queues
+    Queue dq = queue_open(k.st->qctr3, D, 1);
     WaveStats ws;
-    for (int item = ar.i; item < ar.end; item += ar.stride) {
+    for (int item = queue_next(dq); item >= 0; item = queue_next(dq)) {
         const int a = uni(k.dfr[item]);
         Member M = member(k.g, k.ga, k.ca, a);
         const double4 ds = k.dstate[a];
