@@ -1072,7 +1072,7 @@ __global__ void k_reuse_check(const unsigned long long *drift, DevStatus *st)
 
 // One wave per group: the walk, the superset straight into the global
 // buffer, the group record and the member -> group map.
-__global__ __launch_bounds__(64) void k_walk(WalkK k)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_walk(WalkK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const int T = k.ga.T;
@@ -2687,7 +2687,7 @@ constexpr int HQB = 8; // members per take in the hydro member kernel's dynamic 
 // the pairs streamed through the FIFO into the force sums.  Members the
 // superset does not cover are listed for k_hydro_solo.
 template <int KER, typename ACC, int PHYS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? (PHYS ? 4 : 5) : 1))) void k_hmem(HydroK k)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(ACC) == 4 ? 4 : 1))) void k_hmem(HydroK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const unsigned long long t_start = wall_clock64();
