@@ -1181,7 +1181,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
 namespace {
 
 // ------------------------------------------------------------------ per-member set-up
-constexpr int FIFO_B = 4; // neighbour batches of 64 consumed together
+constexpr int FIFO_B = 2; // neighbour batches of 64 consumed together
 
 // LDS of one member wave (the passes of members that walk alone):
 // neighbour masks of the last filter pass, the FIFO and the squared-distance
