@@ -2284,8 +2284,9 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
 // (radius: the bracket's upper end, or 1.25 h while there is none), walked
 // up to three times, and the h loop continued on it from where the group
 // left it; only when that fails too does it walk once per h evaluation.
+constexpr int SOLO_PER_CU = 5; // workgroups of k_dens_solo per CU
 template <int KER, typename ACC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_dens_solo(DensK k)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SOLO_PER_CU))) void k_dens_solo(DensK k)
 {
     extern __shared__ __align__(16) char lds_raw[];
     const MemLds S = mem_carve(lds_raw, k.ga.T, true);
@@ -3073,18 +3074,19 @@ hipError_t run_density(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     const size_t lds_s = MEM_WAVES * mem_lds_bytes(T, true);
     hipError_t e = allow_lds(ks, lds_s);
     if (e != hipSuccess) return e;
-    // the members that leave their group are few but walk the tree alone,
-    // latency bound: four workgroups per CU, each wave with a private slot
-    // when the slots fit in half the buffer (else one workgroup per CU with
-    // slots, else four without)
-    unsigned grid_s = (unsigned)((4 * sb.cu_count + 7) / 8 * 8);
+    // the members that leave their group walk the tree alone, latency
+    // bound: SOLO_PER_CU workgroups per CU (five waves per SIMD, as many as
+    // fit its registers without spills), each wave
+    // with a private slot; fewer workgroups when the slots would take more
+    // than half the buffer, and SOLO_PER_CU without slots when not even one
+    // per CU fits
+    int per_cu = SOLO_PER_CU;
+    while (per_cu > 1 && (int64_t)per_cu * sb.cu_count * MEM_WAVES * T > sb.cand_cap / 2) per_cu--;
+    unsigned grid_s = (unsigned)((per_cu * sb.cu_count + 7) / 8 * 8);
     int64_t priv = (int64_t)grid_s * MEM_WAVES * T;
     if (priv > sb.cand_cap / 2) {
-        const unsigned g1 = (unsigned)((sb.cu_count + 7) / 8 * 8);
-        if ((int64_t)g1 * MEM_WAVES * T <= sb.cand_cap / 2) {
-            grid_s = g1;
-            priv = (int64_t)g1 * MEM_WAVES * T;
-        }
+        grid_s = (unsigned)((SOLO_PER_CU * sb.cu_count + 7) / 8 * 8);
+        priv = sb.cand_cap; // no private slots
     }
     SearchBufs gs = sb;
     if (priv <= sb.cand_cap / 2) gs.cand_cap = sb.cand_cap - priv;
