@@ -274,16 +274,18 @@ __device__ __forceinline__ Queue queue_open(int32_t *ctr, int n_items, int qb = 
     q.cur = q.end = 0;
     return q;
 }
-// Items per take: the walk takes GQB groups per atomic; the density group
-// kernel too when it has many groups per workgroup (at least GQ_MANY each),
-// so the atomics are fewer and the few items that one take holds back at
-// the end are a small part of a taker's work; otherwise one (its groups
-// cost more and vary more, and a held-back one would lengthen the tail).
+// Items per take: GQB per atomic when there are many items per taker (the
+// walk: at least WQ_MANY per wave; the density group kernel: at least
+// GQ_MANY per workgroup, its groups cost more and vary more), so the
+// atomics are fewer and the few items that one take holds back at the end
+// are a small part of a taker's work; otherwise one, so that every taker
+// gets work when the items are few.
 constexpr int GQB = 4;
+constexpr int WQ_MANY = 8;
 constexpr int GQ_MANY = 256;
-__device__ __forceinline__ int queue_qb(int n_items, int takers, int qb)
+__device__ __forceinline__ int queue_qb(int n_items, int takers, int qb, int many)
 {
-    return (int64_t)n_items >= (int64_t)GQ_MANY * takers ? qb : 1;
+    return (int64_t)n_items >= (int64_t)many * takers ? qb : 1;
 }
 // next item, or -1 when every range is used up
 __device__ __forceinline__ int queue_next(Queue &q)
@@ -1079,7 +1081,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7))) void k_
     int *lst = (int *)lds_raw; // [2 * LCAP + 64]: item lists of the level walk, owner marks
     const int lane = lane_id();
     const int G = uni(*k.ga.n_groups);
-    Queue wq = queue_open(k.st->qctr, G, GQB);
+    Queue wq = queue_open(k.st->qctr, G, queue_qb(G, (int)gridDim.x, GQB, WQ_MANY));
     WaveStats ws;
     // candidates are placed in chunks taken by this wave: up to 8192 slots,
     // at most a quarter of a wave's fair share of the buffer, at least a tile
@@ -1846,7 +1848,7 @@ __device__ __forceinline__ int wg_resolve(WgTake &w)
 __device__ __forceinline__ WgTake wg_open(int32_t *ctr, int n_items, const int32_t *gl)
 {
     WgTake w;
-    w.q = queue_open(ctr, n_items, queue_qb(n_items, (int)gridDim.x, GQB));
+    w.q = queue_open(ctr, n_items, queue_qb(n_items, (int)gridDim.x, GQB, GQ_MANY));
     w.gl = gl;
     w.next = threadIdx.x < 64 ? wg_resolve(w) : -1;
     return w;
