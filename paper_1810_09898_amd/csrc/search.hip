@@ -3038,7 +3038,10 @@ hipError_t launch_walk(hipStream_t s, const PartDev &p, const TreeDev &t, const 
     k.skin = skin;
     k.hydro = hydro;
     const size_t lds = (size_t)4 * (2 * LCAP + 64);
-    return launch_persistent(k_walk, s, k, 64, lds, sb.cu_count, p.n);
+    // every wave that takes a group first takes a chunk of at least T slots
+    // of the buffer: no more waves than half the buffer has chunks for
+    const int64_t waves = min(p.n, max((int64_t)8, sb.cand_cap / (2 * (int64_t)T)));
+    return launch_persistent(k_walk, s, k, 64, lds, sb.cu_count, waves);
 }
 
 // the drift bounds of kept supersets and the active count into
